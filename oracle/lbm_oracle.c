@@ -1,0 +1,669 @@
+/*
+ * FP64 CPU oracle for the 13-moment double-distribution lattice Boltzmann step
+ * on D3Q39 (Latt, Coreixas, Beny, Parmigiani, "Efficient supersonic flows
+ * through high-order guided equilibrium with lattice Boltzmann", 2019).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * reference that the HIP library is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark load it; the
+ * library never does.  It shares no source with the HIP path.
+ *
+ * Every routine follows the paper's statement of the method in the order the
+ * paper gives it, with no blocking, fusion or reordering:
+ *   - velocity set: Sec. 3, the E_{3,7}^{39} lattice (D3Q39);
+ *   - Maxwell-Boltzmann target moments: Sec. 2, Eq. (eq:EqMomentsTensor),
+ *     with the 13 constraints of Eq. (eq:13constraints);
+ *   - exponential equilibrium: Sec. 2, Eq. (eq:discrete-equilibrium);
+ *   - Newton-Raphson for the Lagrange multipliers: Sec. 3 and the algorithm
+ *     table of Sec. 5 (warm start from the previous time step);
+ *   - polyatomic second population: Eq. (eq:discrete-equilibrium-poly);
+ *   - Knudsen sensor: Eq. (eq:DeltaAvg); relaxation factor: Eq. (eq:alpha);
+ *   - BGK collide-and-stream for h = f, g with Pr = 1: Sec. 3;
+ *   - free-stream equilibrium faces, first-order Neumann outlet and half-way
+ *     bounce-back: Sec. 4 (NACA0012 set-up).
+ * Readings where the paper is silent or garbled are marked "reading:".
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NQ 39   /* discrete velocities */
+#define NL 13   /* Lagrange multipliers / constraints */
+#define DIM 3   /* the lattice is three-dimensional for every grid */
+
+/* ------------------------------------------------------------------------ */
+/* Lattice (Sec. 3): (0,0,0), (1,0,0)_FS, (+-1,+-1,+-1), (2,0,0)_FS,          */
+/* (2,2,0)_FS, (3,0,0)_FS.  Listed so that for every odd i, velocity i+1 is   */
+/* the opposite of velocity i (an interface convention of the library).       */
+/* ------------------------------------------------------------------------ */
+static const int VEL[NQ][3] = {
+    {0, 0, 0},
+    {1, 0, 0},   {-1, 0, 0},  {0, 1, 0},   {0, -1, 0},  {0, 0, 1},   {0, 0, -1},
+    {1, 1, 1},   {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1}, {1, -1, 1}, {-1, 1, -1},
+    {-1, 1, 1},  {1, -1, -1},
+    {2, 0, 0},   {-2, 0, 0},  {0, 2, 0},   {0, -2, 0},  {0, 0, 2},   {0, 0, -2},
+    {2, 2, 0},   {-2, -2, 0}, {2, -2, 0},  {-2, 2, 0},  {2, 0, 2},   {-2, 0, -2},
+    {2, 0, -2},  {-2, 0, 2},  {0, 2, 2},   {0, -2, -2}, {0, 2, -2},  {0, -2, 2},
+    {3, 0, 0},   {-3, 0, 0},  {0, 3, 0},   {0, -3, 0},  {0, 0, 3},   {0, 0, -3},
+};
+
+static int opposite(int i)
+{
+    int j;
+    for (j = 0; j < NQ; ++j)
+        if (VEL[j][0] == -VEL[i][0] && VEL[j][1] == -VEL[i][1] && VEL[j][2] == -VEL[i][2])
+            return j;
+    return -1;
+}
+
+/* Basis of the 13-moment exponent, Eq. (eq:discrete-equilibrium):
+ * 1, xi_a (3), xi_a xi_b for a <= b (6), xi_a |xi|^2 (3).  The multiplier of
+ * the off-diagonal product xi_a xi_b absorbs the factor 2 of the symmetric
+ * double sum; only f^eq is observable, so the parameterisation is free. */
+static void basis(const double c[3], double phi[NL])
+{
+    double q = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+    phi[0] = 1.0;
+    phi[1] = c[0];
+    phi[2] = c[1];
+    phi[3] = c[2];
+    phi[4] = c[0] * c[0];
+    phi[5] = c[1] * c[1];
+    phi[6] = c[2] * c[2];
+    phi[7] = c[0] * c[1];
+    phi[8] = c[0] * c[2];
+    phi[9] = c[1] * c[2];
+    phi[10] = c[0] * q;
+    phi[11] = c[1] * q;
+    phi[12] = c[2] * q;
+}
+
+static double PHI[NQ][NL];
+static int OPP[NQ];
+static int tables_ready = 0;
+
+static void make_tables(void)
+{
+    int i;
+    if (tables_ready) return;
+    for (i = 0; i < NQ; ++i) {
+        double c[3] = {VEL[i][0], VEL[i][1], VEL[i][2]};
+        basis(c, PHI[i]);
+        OPP[i] = opposite(i);
+    }
+    tables_ready = 1;
+}
+
+/* Maxwell-Boltzmann moments per unit density, Eq. (eq:EqMomentsTensor),
+ * restricted to the 13 constraints of Eq. (eq:13constraints).
+ * Reading: the contracted third moment is sum_b M3_abb = rho u_a (|u|^2 +
+ * (D+2) T), which is what contracting the printed third-order tensor gives;
+ * the printed "E^tr = D T + rho u^2" is dimensionally garbled. */
+static void mb_targets(const double u[3], double T, double m[NL])
+{
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    double h = uu + (DIM + 2) * T;
+    m[0] = 1.0;
+    m[1] = u[0];
+    m[2] = u[1];
+    m[3] = u[2];
+    m[4] = u[0] * u[0] + T;
+    m[5] = u[1] * u[1] + T;
+    m[6] = u[2] * u[2] + T;
+    m[7] = u[0] * u[1];
+    m[8] = u[0] * u[2];
+    m[9] = u[1] * u[2];
+    m[10] = h * u[0];
+    m[11] = h * u[1];
+    m[12] = h * u[2];
+}
+
+/* f^eq_i / rho = exp(phi_i . lambda) for the current multipliers, and the
+ * constraint residual G = sum_i f^eq_i phi_i / rho - M/rho, Eq. (eq:constraints). */
+static void equilibrium_and_residual(const double lam[NL], const double m[NL], double feq[NQ], double G[NL])
+{
+    int i, k;
+    for (i = 0; i < NQ; ++i) {
+        double e = 0.0;
+        for (k = 0; k < NL; ++k) e += PHI[i][k] * lam[k];
+        feq[i] = exp(e);
+    }
+    for (k = 0; k < NL; ++k) {
+        double s = 0.0;
+        for (i = 0; i < NQ; ++i) s += feq[i] * PHI[i][k];
+        G[k] = s - m[k];
+    }
+}
+
+/* Jacobian of G with respect to lambda: J_kl = sum_i f^eq_i phi_ik phi_il. */
+static void jacobian(const double feq[NQ], double J[NL][NL])
+{
+    int i, k, l;
+    for (k = 0; k < NL; ++k)
+        for (l = 0; l < NL; ++l) {
+            double s = 0.0;
+            for (i = 0; i < NQ; ++i) s += feq[i] * PHI[i][k] * PHI[i][l];
+            J[k][l] = s;
+        }
+}
+
+/* Solve J d = G.  The paper inverts J; J is symmetric positive definite
+ * (a Gram matrix of 13 linearly independent functions on 39 velocities), so a
+ * Cholesky solve gives the same d.  Returns 0 on success. */
+static int cholesky_solve(double J[NL][NL], const double G[NL], double d[NL])
+{
+    double L[NL][NL];
+    double y[NL];
+    int i, j, k;
+    memset(L, 0, sizeof(L));
+    for (j = 0; j < NL; ++j) {
+        double s = J[j][j];
+        for (k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
+        if (!(s > 0.0)) return -1;
+        L[j][j] = sqrt(s);
+        for (i = j + 1; i < NL; ++i) {
+            double t = J[i][j];
+            for (k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+            L[i][j] = t / L[j][j];
+        }
+    }
+    for (i = 0; i < NL; ++i) {
+        double t = G[i];
+        for (k = 0; k < i; ++k) t -= L[i][k] * y[k];
+        y[i] = t / L[i][i];
+    }
+    for (i = NL - 1; i >= 0; --i) {
+        double t = y[i];
+        for (k = i + 1; k < NL; ++k) t -= L[k][i] * d[k];
+        d[i] = t / L[i][i];
+    }
+    return 0;
+}
+
+static double norm_inf(const double v[NL])
+{
+    double r = 0.0;
+    int k;
+    for (k = 0; k < NL; ++k) {
+        double a = fabs(v[k]);
+        if (!(a <= r)) r = a; /* NaN propagates */
+    }
+    return r;
+}
+
+static double norm_2(const double v[NL])
+{
+    double r = 0.0;
+    int k;
+    for (k = 0; k < NL; ++k) r += v[k] * v[k];
+    return sqrt(r);
+}
+
+/* Cold start of the multipliers at t = 0 (reading: the paper only gives the
+ * warm start from t - 1): the Maxwellian shape lambda_1 = u/T,
+ * lambda_2 = -delta/(2T), lambda_3 = 0, lambda_0 normalising the sum to 1. */
+static void cold_guess(const double u[3], double T, double lam[NL])
+{
+    double s = 0.0;
+    int i, k;
+    for (k = 0; k < NL; ++k) lam[k] = 0.0;
+    lam[1] = u[0] / T;
+    lam[2] = u[1] / T;
+    lam[3] = u[2] / T;
+    lam[4] = lam[5] = lam[6] = -0.5 / T;
+    for (i = 0; i < NQ; ++i) {
+        double e = 0.0;
+        for (k = 1; k < NL; ++k) e += PHI[i][k] * lam[k];
+        s += exp(e);
+    }
+    lam[0] = -log(s);
+}
+
+/* Newton-Raphson for the 13 multipliers (Sec. 5 algorithm table): evaluate
+ * f^eq and G; stop when the error norm is below tol; otherwise build J, solve,
+ * and step.  Reading of the stopping norm: max_k |G_k| / rho <=
+ * tol * max(1, max_k |M_k| / rho).  Globalisation (reading; the paper says
+ * only "standard multivariate Newton-Raphson"): the step is halved while the
+ * Euclidean norm of G does not decrease.  On return lam and feq (per unit
+ * density) hold the last iterate.  Returns the number of accepted updates,
+ * or -1 when the cap is reached, J is not positive definite, or a value is
+ * not finite. */
+static int newton(const double m[NL], double lam[NL], double feq[NQ], double tol, int maxit)
+{
+    double G[NL], J[NL][NL], d[NL], trial[NL], Gt[NL], ft[NQ];
+    double scale = 1.0;
+    int it, k, ls;
+    for (k = 0; k < NL; ++k)
+        if (fabs(m[k]) > scale) scale = fabs(m[k]);
+    equilibrium_and_residual(lam, m, feq, G);
+    for (it = 0;; ++it) {
+        double r = norm_inf(G);
+        double n0;
+        if (!isfinite(r)) return -1;
+        if (r <= tol * scale) return it;
+        if (it >= maxit) return -1;
+        jacobian(feq, J);
+        if (cholesky_solve(J, G, d) != 0) return -1;
+        n0 = norm_2(G);
+        {
+            double t = 1.0;
+            for (ls = 0; ls < 40; ++ls) {
+                for (k = 0; k < NL; ++k) trial[k] = lam[k] - t * d[k];
+                equilibrium_and_residual(trial, m, ft, Gt);
+                if (norm_2(Gt) < n0) break;
+                t *= 0.5;
+            }
+        }
+        for (k = 0; k < NL; ++k) {
+            lam[k] = trial[k];
+            G[k] = Gt[k];
+        }
+        for (k = 0; k < NQ; ++k) feq[k] = ft[k];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Public interface (ctypes)                                                */
+/* ------------------------------------------------------------------------ */
+
+enum { FACE_PERIODIC = 0, FACE_EQUILIBRIUM = 1, FACE_NEUMANN = 2 };
+enum { CELL_FLUID = 0, CELL_SOLID = 1, CELL_FROZEN = 2, CELL_NEUMANN = 3 };
+
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t kn_relax;      /* 1: tau * alpha(eps), Eq. (eq:alpha); 0: plain BGK */
+    int32_t newton_maxit;
+    int32_t faces[6];      /* -x, +x, -y, +y, -z, +z */
+    double gamma;          /* C_v = 1/(gamma - 1) */
+    double tau;
+    double newton_tol;
+    const uint8_t *solid;  /* nx*ny*nz or NULL */
+} orc_params;
+
+typedef struct {
+    int64_t iterations;    /* accepted Newton updates, summed over fluid cells */
+    int64_t max_iterations;
+    int64_t failed;        /* cells whose Newton did not converge */
+    int64_t alpha_hist[4]; /* cells per branch of Eq. (eq:alpha) */
+    int64_t cold_restarts; /* cells that fell back to the cold start */
+} orc_stats;
+
+void orc_velocities(int32_t *out)
+{
+    int i;
+    for (i = 0; i < NQ; ++i) {
+        out[3 * i + 0] = VEL[i][0];
+        out[3 * i + 1] = VEL[i][1];
+        out[3 * i + 2] = VEL[i][2];
+    }
+}
+
+static double heat_capacity(double gamma) { return 1.0 / (gamma - 1.0); }
+
+/* Equilibrium of one cell: returns iterations (or -1); writes lam (in/out:
+ * used as the warm start unless cold != 0) and f^eq, g^eq (not per unit
+ * density).  g^eq = (2 C_v - D) T f^eq, Eq. (eq:discrete-equilibrium-poly). */
+int orc_equilibrium(double rho, const double *u, double T, double gamma, double *lam, int cold, double tol,
+                    int maxit, double *feq_out, double *geq_out)
+{
+    double m[NL], feq[NQ];
+    double delta = 2.0 * heat_capacity(gamma) - DIM;
+    int it, i;
+    make_tables();
+    mb_targets(u, T, m);
+    if (cold) cold_guess(u, T, lam);
+    it = newton(m, lam, feq, tol, maxit);
+    for (i = 0; i < NQ; ++i) {
+        if (feq_out) feq_out[i] = rho * feq[i];
+        if (geq_out) geq_out[i] = delta * T * rho * feq[i];
+    }
+    return it;
+}
+
+static int64_t cell_index(const orc_params *p, int x, int y, int z)
+{
+    return (int64_t)x + (int64_t)p->nx * ((int64_t)y + (int64_t)p->ny * z);
+}
+
+static int wrap(int a, int n)
+{
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+/* Cell classification.  Reading of the face conditions with a three-cell
+ * reach: the three outermost layers of a non-periodic face are boundary
+ * cells.  Equilibrium faces hold the equilibrium of their initial state and
+ * are never updated; Neumann faces copy the nearest interior cell before each
+ * step (first-order zero gradient).  Equilibrium takes precedence where an
+ * equilibrium face and a Neumann face meet. */
+static int in_face_layer(const orc_params *p, int x, int y, int z, int kind)
+{
+    int n[3] = {p->nx, p->ny, p->nz};
+    int c[3] = {x, y, z};
+    int a;
+    for (a = 0; a < 3; ++a) {
+        if (p->faces[2 * a] == kind && c[a] < 3) return 1;
+        if (p->faces[2 * a + 1] == kind && c[a] >= n[a] - 3) return 1;
+    }
+    return 0;
+}
+
+static int cell_type(const orc_params *p, int x, int y, int z)
+{
+    if (p->solid && p->solid[cell_index(p, x, y, z)]) return CELL_SOLID;
+    if (in_face_layer(p, x, y, z, FACE_EQUILIBRIUM)) return CELL_FROZEN;
+    if (in_face_layer(p, x, y, z, FACE_NEUMANN)) return CELL_NEUMANN;
+    return CELL_FLUID;
+}
+
+void orc_cell_types(const orc_params *p, uint8_t *out)
+{
+    int x, y, z;
+    for (z = 0; z < p->nz; ++z)
+        for (y = 0; y < p->ny; ++y)
+            for (x = 0; x < p->nx; ++x) out[cell_index(p, x, y, z)] = (uint8_t)cell_type(p, x, y, z);
+}
+
+/* The cell whose populations a Neumann boundary cell copies: its coordinates
+ * clamped into the interior along every Neumann axis. */
+static int64_t neumann_source(const orc_params *p, int x, int y, int z)
+{
+    int n[3] = {p->nx, p->ny, p->nz};
+    int c[3] = {x, y, z};
+    int a;
+    for (a = 0; a < 3; ++a) {
+        if (p->faces[2 * a] == FACE_NEUMANN && c[a] < 3) c[a] = 3;
+        if (p->faces[2 * a + 1] == FACE_NEUMANN && c[a] >= n[a] - 3) c[a] = n[a] - 4;
+    }
+    return cell_index(p, c[0], c[1], c[2]);
+}
+
+/* Neighbour coordinate along one axis: periodic axes wrap; on other axes the
+ * three boundary layers guarantee that interior cells stay inside. */
+static int step_axis(const orc_params *p, int a, int c, int d)
+{
+    int n = a == 0 ? p->nx : (a == 1 ? p->ny : p->nz);
+    int lo = p->faces[2 * a], hi = p->faces[2 * a + 1];
+    if (lo == FACE_PERIODIC && hi == FACE_PERIODIC) return wrap(c + d, n);
+    return c + d;
+}
+
+/* Primitive direction and multiplicity of a velocity: xi = mult * dir. */
+static int multiplicity(int i)
+{
+    int a, g = 0;
+    for (a = 0; a < 3; ++a) {
+        int v = abs(VEL[i][a]);
+        if (v > g) g = v;
+    }
+    /* every D3Q39 velocity is a multiple of a vector with entries in {-1,0,1} */
+    return g;
+}
+
+/* Pull streaming of population i into fluid cell (x,y,z) (the push form of
+ * Sec. 3 written as a gather).  Half-way bounce-back for multi-speed links
+ * (reading; the paper states half-way bounce-back only): the link is blocked
+ * when any lattice node passed over, x - k dir_i for k = 1..mult_i, is
+ * solid; the cell then receives its own post-collision population of the
+ * opposite direction. */
+static int64_t pull_source(const orc_params *p, int x, int y, int z, int i, int *bounced)
+{
+    int m = multiplicity(i);
+    int d[3], k, a;
+    int c[3] = {x, y, z};
+    for (a = 0; a < 3; ++a) d[a] = VEL[i][a] / (m == 0 ? 1 : m);
+    *bounced = 0;
+    if (m == 0) return cell_index(p, x, y, z);
+    if (p->solid) {
+        for (k = 1; k <= m; ++k) {
+            int s[3];
+            for (a = 0; a < 3; ++a) s[a] = step_axis(p, a, c[a], -k * d[a]);
+            if (p->solid[cell_index(p, s[0], s[1], s[2])]) {
+                *bounced = 1;
+                return cell_index(p, x, y, z);
+            }
+        }
+    }
+    {
+        int s[3];
+        for (a = 0; a < 3; ++a) s[a] = step_axis(p, a, c[a], -VEL[i][a]);
+        if (cell_type(p, s[0], s[1], s[2]) == CELL_NEUMANN) return neumann_source(p, s[0], s[1], s[2]);
+        return cell_index(p, s[0], s[1], s[2]);
+    }
+}
+
+/* Macroscopic variables of one cell from its populations (Sec. 3 and the
+ * first row of the Sec. 5 table).  Reading (the paper does not write T out):
+ * total energy 2 rho E = sum f |xi|^2 + sum g, with E = |u|^2/2 + C_v T
+ * (equation of state under Eq. (eq:NSF)). */
+static void macroscopic(const double f[NQ], const double g[NQ], double gamma, double *rho, double u[3], double *T)
+{
+    double r = 0.0, j[3] = {0.0, 0.0, 0.0}, e = 0.0, uu;
+    int i, a;
+    for (i = 0; i < NQ; ++i) {
+        r += f[i];
+        for (a = 0; a < 3; ++a) j[a] += f[i] * VEL[i][a];
+        e += f[i] * (VEL[i][0] * VEL[i][0] + VEL[i][1] * VEL[i][1] + VEL[i][2] * VEL[i][2]);
+        e += g[i];
+    }
+    for (a = 0; a < 3; ++a) u[a] = j[a] / r;
+    uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    *rho = r;
+    *T = (e - r * uu) / (2.0 * heat_capacity(gamma) * r);
+}
+
+/* Relaxation factor alpha(eps) of Eq. (eq:alpha); intervals closed on the
+ * left as printed.  Returns the branch index 0..3. */
+static int alpha_branch(double eps)
+{
+    if (eps < 1e-2) return 0;
+    if (eps < 1e-1) return 1;
+    if (eps < 1.0) return 2;
+    return 3; /* also NaN/inf: the cell is replaced by its equilibrium */
+}
+
+/* Initial state: every cell holds the equilibrium of its (rho, u, T) field,
+ * computed with the cold start; the multipliers are stored for the warm start.
+ * Returns the number of cells whose Newton did not converge. */
+int64_t orc_init(const orc_params *p, const double *rho, const double *u, const double *T, double *f, double *g,
+                 double *lam)
+{
+    int64_t n = (int64_t)p->nx * p->ny * p->nz;
+    int64_t c, failed = 0;
+    make_tables();
+#pragma omp parallel for reduction(+ : failed) schedule(dynamic, 64)
+    for (c = 0; c < n; ++c) {
+        double uc[3] = {u[c], u[n + c], u[2 * n + c]};
+        double l[NL], fe[NQ], ge[NQ];
+        int i, k, maxit = p->newton_maxit > 100 ? p->newton_maxit : 100;
+        int it = orc_equilibrium(rho[c], uc, T[c], p->gamma, l, 1, p->newton_tol, maxit, fe, ge);
+        if (it < 0) failed += 1;
+        for (i = 0; i < NQ; ++i) {
+            f[i * n + c] = fe[i];
+            g[i * n + c] = ge[i];
+        }
+        for (k = 0; k < NL; ++k) lam[k * n + c] = l[k];
+    }
+    return failed;
+}
+
+/* One time step: for every fluid cell, stream (pull), compute the
+ * macroscopic variables, the Maxwell-Boltzmann targets, the multipliers by
+ * Newton from the stored ones, f^eq and g^eq, the Knudsen sensor and the
+ * relaxation factor, and write the BGK-relaxed populations.  Boundary and
+ * solid cells are copied unchanged.  iters_out / eps_out (length N, or NULL)
+ * receive per-cell diagnostics (-1 / NaN outside fluid cells). */
+void orc_step(const orc_params *p, const double *f, const double *g, const double *lam, double *fo, double *go,
+              double *lamo, int32_t *iters_out, double *eps_out, orc_stats *st)
+{
+    int64_t n = (int64_t)p->nx * p->ny * p->nz;
+    int64_t c;
+    int64_t s_it = 0, s_max = 0, s_fail = 0, s_cold = 0, h0 = 0, h1 = 0, h2 = 0, h3 = 0;
+    double Cv = heat_capacity(p->gamma);
+    double delta = 2.0 * Cv - DIM;
+    make_tables();
+#pragma omp parallel for schedule(dynamic, 64) \
+    reduction(+ : s_it, s_fail, s_cold, h0, h1, h2, h3) reduction(max : s_max)
+    for (c = 0; c < n; ++c) {
+        int x = (int)(c % p->nx);
+        int y = (int)((c / p->nx) % p->ny);
+        int z = (int)(c / ((int64_t)p->nx * p->ny));
+        int i, k, it, br, bounced;
+        double fi[NQ], gi[NQ], l[NL], m[NL], feq[NQ], geq[NQ];
+        double rho, u[3], T, eps, tau_eff, omega;
+        if (cell_type(p, x, y, z) != CELL_FLUID) {
+            for (i = 0; i < NQ; ++i) {
+                fo[i * n + c] = f[i * n + c];
+                go[i * n + c] = g[i * n + c];
+            }
+            for (k = 0; k < NL; ++k) lamo[k * n + c] = lam[k * n + c];
+            if (iters_out) iters_out[c] = -1;
+            if (eps_out) eps_out[c] = NAN;
+            continue;
+        }
+        /* streaming */
+        for (i = 0; i < NQ; ++i) {
+            int64_t s = pull_source(p, x, y, z, i, &bounced);
+            int src_pop = bounced ? OPP[i] : i;
+            fi[i] = f[src_pop * n + s];
+            gi[i] = g[src_pop * n + s];
+        }
+        /* macroscopic variables and targets */
+        macroscopic(fi, gi, p->gamma, &rho, u, &T);
+        mb_targets(u, T, m);
+        /* multipliers: warm start from the previous step */
+        for (k = 0; k < NL; ++k) l[k] = lam[k * n + c];
+        it = newton(m, l, feq, p->newton_tol, p->newton_maxit);
+        if (it < 0) {
+            /* reading: a failed warm start is retried once from the cold
+             * start before the cell is counted as failed */
+            int it2;
+            s_cold += 1;
+            cold_guess(u, T, l);
+            it2 = newton(m, l, feq, p->newton_tol, p->newton_maxit > 100 ? p->newton_maxit : 100);
+            if (it2 < 0) {
+                s_fail += 1;
+                it = p->newton_maxit;
+            } else {
+                it = it2;
+            }
+        }
+        s_it += it;
+        if (it > s_max) s_max = it;
+        for (i = 0; i < NQ; ++i) {
+            feq[i] *= rho;
+            geq[i] = delta * T * feq[i];
+        }
+        /* Knudsen sensor over f only, Eq. (eq:DeltaAvg) */
+        eps = 0.0;
+        for (i = 0; i < NQ; ++i) eps += fabs(fi[i] - feq[i]) / feq[i];
+        eps /= NQ;
+        br = p->kn_relax ? alpha_branch(eps) : 0;
+        if (br == 0) h0 += 1;
+        else if (br == 1) h1 += 1;
+        else if (br == 2) h2 += 1;
+        else h3 += 1;
+        /* tau(eps) = tau * alpha(eps); alpha = 1/tau gives tau_eff = 1 */
+        if (br == 0) tau_eff = p->tau;
+        else if (br == 1) tau_eff = p->tau * 1.05;
+        else if (br == 2) tau_eff = p->tau * 1.35;
+        else tau_eff = 1.0;
+        omega = 1.0 / tau_eff;
+        /* BGK, the same relaxation time for f and g (Pr = 1) */
+        for (i = 0; i < NQ; ++i) {
+            fo[i * n + c] = fi[i] + omega * (feq[i] - fi[i]);
+            go[i * n + c] = gi[i] + omega * (geq[i] - gi[i]);
+        }
+        for (k = 0; k < NL; ++k) lamo[k * n + c] = l[k];
+        if (iters_out) iters_out[c] = it;
+        if (eps_out) eps_out[c] = eps;
+    }
+    if (st) {
+        st->iterations = s_it;
+        st->max_iterations = s_max;
+        st->failed = s_fail;
+        st->cold_restarts = s_cold;
+        st->alpha_hist[0] = h0;
+        st->alpha_hist[1] = h1;
+        st->alpha_hist[2] = h2;
+        st->alpha_hist[3] = h3;
+    }
+}
+
+/* Pure streaming (no collision) of one population array, with the same
+ * boundary rules as orc_step; used to check that the gather is a permutation. */
+void orc_stream_only(const orc_params *p, const double *f, double *fo)
+{
+    int64_t n = (int64_t)p->nx * p->ny * p->nz;
+    int64_t c;
+    make_tables();
+    for (c = 0; c < n; ++c) {
+        int x = (int)(c % p->nx);
+        int y = (int)((c / p->nx) % p->ny);
+        int z = (int)(c / ((int64_t)p->nx * p->ny));
+        int i, bounced;
+        for (i = 0; i < NQ; ++i) {
+            if (cell_type(p, x, y, z) != CELL_FLUID) {
+                fo[i * n + c] = f[i * n + c];
+            } else {
+                int64_t s = pull_source(p, x, y, z, i, &bounced);
+                fo[i * n + c] = f[(bounced ? OPP[i] : i) * n + s];
+            }
+        }
+    }
+}
+
+/* Macroscopic fields of the stored populations: out = [rho, ux, uy, uz, T]
+ * (each N, NaN at solid cells; Neumann cells report the cell they copy).
+ * totals = [mass, momentum x, y, z, total energy sum (f|xi|^2 + g)/2] over
+ * fluid cells. */
+void orc_moments(const orc_params *p, const double *f, const double *g, double *out, double *totals)
+{
+    int64_t n = (int64_t)p->nx * p->ny * p->nz;
+    int64_t c;
+    double tm = 0.0, tx = 0.0, ty = 0.0, tz = 0.0, te = 0.0;
+    make_tables();
+    for (c = 0; c < n; ++c) {
+        int x = (int)(c % p->nx);
+        int y = (int)((c / p->nx) % p->ny);
+        int z = (int)(c / ((int64_t)p->nx * p->ny));
+        int t = cell_type(p, x, y, z);
+        int64_t s = c;
+        double fi[NQ], gi[NQ], rho, u[3], T;
+        int i;
+        if (t == CELL_SOLID) {
+            for (i = 0; i < 5; ++i) out[i * n + c] = NAN;
+            continue;
+        }
+        if (t == CELL_NEUMANN) s = neumann_source(p, x, y, z);
+        for (i = 0; i < NQ; ++i) {
+            fi[i] = f[i * n + s];
+            gi[i] = g[i * n + s];
+        }
+        macroscopic(fi, gi, p->gamma, &rho, u, &T);
+        out[c] = rho;
+        out[n + c] = u[0];
+        out[2 * n + c] = u[1];
+        out[3 * n + c] = u[2];
+        out[4 * n + c] = T;
+        if (t == CELL_FLUID) {
+            double e = 0.0;
+            for (i = 0; i < NQ; ++i)
+                e += fi[i] * (VEL[i][0] * VEL[i][0] + VEL[i][1] * VEL[i][1] + VEL[i][2] * VEL[i][2]) + gi[i];
+            tm += rho;
+            tx += rho * u[0];
+            ty += rho * u[1];
+            tz += rho * u[2];
+            te += 0.5 * e;
+        }
+    }
+    if (totals) {
+        totals[0] = tm;
+        totals[1] = tx;
+        totals[2] = ty;
+        totals[3] = tz;
+        totals[4] = te;
+    }
+}

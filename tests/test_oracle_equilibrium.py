@@ -1,0 +1,248 @@
+"""Pins of the oracle's equilibrium (CPU only).
+
+Each check compares the oracle with something other than itself:
+  * the velocity set against the families listed in the paper (Sec. 3);
+  * the 13 constraint moments against Gauss-Hermite quadrature of the
+    continuous Maxwell-Boltzmann distribution (Sec. 2, Eq. eq:EqMomentsTensor);
+  * the rest state (u = 0) against a one-dimensional root find;
+  * general states against a 30-digit mpmath solve of the same constraints;
+  * existence against a linear-programming feasibility test of the moment cone;
+  * cubic symmetry, density scaling and the g^eq identity (Eq.
+    eq:discrete-equilibrium-poly).
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _families_from_paper():
+    with open(os.path.join(GOLDEN, "d3q39_velocity_families.json")) as fh:
+        spec = json.load(fh)
+    vels = set()
+    for gen in spec["fully_symmetric_generators"]:
+        for perm in itertools.permutations(gen):
+            for signs in itertools.product((1, -1), repeat=3):
+                vels.add(tuple(int(s * p) for s, p in zip(signs, perm)))
+    return vels, spec["count"]
+
+
+def test_velocity_set_matches_paper(orc):
+    vels, count = _families_from_paper()
+    got = orc.velocities()
+    assert len(vels) == count == 39
+    assert set(map(tuple, got.tolist())) == vels
+    assert len(set(map(tuple, got.tolist()))) == 39
+    # odd i and i+1 are opposite (the library's interface convention)
+    for i in range(1, 39, 2):
+        assert tuple(got[i]) == tuple(-got[i + 1])
+    assert tuple(got[0]) == (0, 0, 0)
+
+
+def _basis_values(xi):
+    x, y, z = xi[..., 0], xi[..., 1], xi[..., 2]
+    q = x * x + y * y + z * z
+    return np.stack([np.ones_like(x), x, y, z, x * x, y * y, z * z, x * y, x * z, y * z, x * q, y * q, z * q], -1)
+
+
+def _maxwellian_moments(rho, u, T, npts=8):
+    """13 moments of rho (2 pi T)^{-3/2} exp(-|xi - u|^2 / (2T)) by tensor
+    Gauss-Hermite quadrature (exact for these polynomial degrees)."""
+    x, w = np.polynomial.hermite_e.hermegauss(npts)
+    w = w / math.sqrt(2.0 * math.pi)
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    W = w[:, None, None] * w[None, :, None] * w[None, None, :]
+    xi = np.stack([u[0] + math.sqrt(T) * X, u[1] + math.sqrt(T) * Y, u[2] + math.sqrt(T) * Z], -1)
+    phi = _basis_values(xi)
+    return rho * (phi * W[..., None]).sum(axis=(0, 1, 2))
+
+
+def _random_states(seed, count, umax=1.0, Tr=(0.35, 0.9)):
+    rng = np.random.default_rng(seed)
+    for _ in range(count):
+        rho = float(np.exp(rng.uniform(np.log(0.1), np.log(10.0))))
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        u = d * rng.uniform(0.0, umax)
+        T = float(rng.uniform(*Tr))
+        yield rho, u, T
+
+
+def test_thirteen_moments_match_maxwellian(orc):
+    c = orc.velocities().astype(np.float64)
+    phi = _basis_values(c)
+    worst = 0.0
+    tested = 0
+    for rho, u, T in _random_states(1234, 160):
+        if _interior_margin(c, _maxwellian_moments(1.0, u, T)) <= 1e-7:
+            continue  # outside the realizable window (checked separately)
+        tested += 1
+        feq, geq, lam, it = orc.equilibrium(rho, u, T, tol=1e-14)
+        assert it >= 0, (rho, u, T)
+        got = phi.T @ feq
+        ref = _maxwellian_moments(rho, u, T)
+        err = np.max(np.abs(got - ref)) / (rho * max(1.0, np.max(np.abs(ref)) / rho))
+        worst = max(worst, err)
+    assert tested >= 100
+    assert worst < 2e-14, worst
+
+
+def test_maxwellian_sign_and_contracted_heat_flux():
+    """The quadrature reference itself: the contracted third moment equals
+    rho u (|u|^2 + 5 T) (D = 3), which fixes the reading of the garbled
+    translational-energy line, and M2 = rho u u + rho T I."""
+    u = np.array([0.3, -0.2, 0.1])
+    T = 0.45
+    m = _maxwellian_moments(2.0, u, T)
+    uu = float(u @ u)
+    np.testing.assert_allclose(m[10:13], 2.0 * u * (uu + 5 * T), rtol=1e-13)
+    np.testing.assert_allclose(m[4:7], 2.0 * (u * u + T), rtol=1e-13)
+    np.testing.assert_allclose(m[7:10], 2.0 * np.array([u[0] * u[1], u[0] * u[2], u[1] * u[2]]), rtol=1e-13)
+
+
+@pytest.mark.parametrize("T", [0.3, 0.5, 2.0 / 3.0, 1.0])
+def test_rest_state_reduces_to_one_dimensional_root(orc, T):
+    """At u = 0 the odd multipliers vanish by symmetry and the off-diagonal
+    ones too, leaving f_i = rho exp(l0 + l2 |xi_i|^2); l2 solves a monotone
+    scalar equation for the temperature."""
+    from scipy.optimize import brentq
+    c = orc.velocities().astype(np.float64)
+    q = (c ** 2).sum(1)
+
+    def temp(l2):
+        w = np.exp(l2 * q)
+        return (w * c[:, 0] ** 2).sum() / w.sum() - T
+
+    l2 = brentq(temp, -50.0, -1e-6, xtol=1e-17, rtol=1e-15)
+    w = np.exp(l2 * q)
+    ref = w / w.sum()
+    feq, geq, lam, it = orc.equilibrium(1.0, [0.0, 0.0, 0.0], T, tol=1e-14)
+    assert it >= 0
+    np.testing.assert_allclose(feq, ref, rtol=1e-12, atol=0)
+
+
+def _mp_solve(c, m, lam0, dps=32):
+    import mpmath as mp
+    mp.mp.dps = dps
+    phi = [[mp.mpf(v) for v in row] for row in _basis_values(c)]
+    mm = [mp.mpf(v) for v in m]
+
+    def G(*lam):
+        e = [mp.exp(mp.fsum(p[k] * lam[k] for k in range(13))) for p in phi]
+        return [mp.fsum(e[i] * phi[i][k] for i in range(39)) - mm[k] for k in range(13)]
+
+    def J(*lam):
+        e = [mp.exp(mp.fsum(p[k] * lam[k] for k in range(13))) for p in phi]
+        return [[mp.fsum(e[i] * phi[i][k] * phi[i][l] for i in range(39)) for l in range(13)] for k in range(13)]
+
+    sol = mp.findroot(G, [mp.mpf(v) for v in lam0], J=J, tol=mp.mpf(10) ** (-28), maxsteps=60)
+    lam = [sol[k] for k in range(13)]
+    return np.array([float(mp.exp(mp.fsum(p[k] * lam[k] for k in range(13)))) for p in phi])
+
+
+@pytest.mark.parametrize("u,T", [((0.2, -0.1, 0.05), 0.5), ((1.255, 0.0, 0.0), 0.5), ((0.5, 0.4, -0.3), 0.4),
+                                 ((1.6, 0.2, 0.0), 0.6)])
+def test_matches_high_precision_solve(orc, u, T):
+    """Same constraints, independent solver (mpmath multidimensional Newton at
+    32 digits) started from the Maxwellian-shaped guess built here."""
+    c = orc.velocities().astype(np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    m = _maxwellian_moments(1.0, u, T)
+    q = (c ** 2).sum(1)
+    lam0 = np.zeros(13)
+    lam0[1:4] = u / T
+    lam0[4:7] = -0.5 / T
+    lam0[0] = -math.log(np.exp(c @ lam0[1:4] - 0.5 * q / T).sum())
+    ref = _mp_solve(c, m, lam0)
+    feq, _, _, it = orc.equilibrium(1.0, u, T, tol=1e-14)
+    assert it >= 0
+    np.testing.assert_allclose(feq, ref, rtol=1e-11, atol=1e-300)
+
+
+def _interior_margin(c, m):
+    """max t such that some f >= t satisfies the 13 moment equations (LP)."""
+    from scipy.optimize import linprog
+    phi = _basis_values(c)
+    # variables: f (39) and t; maximise t
+    A_eq = np.hstack([phi.T, np.zeros((13, 1))])
+    A_ub = np.hstack([-np.eye(39), np.ones((39, 1))])
+    res = linprog(np.r_[np.zeros(39), -1.0], A_ub=A_ub, b_ub=np.zeros(39), A_eq=A_eq, b_eq=m,
+                  bounds=[(None, None)] * 40, method="highs")
+    if res.status != 0:
+        return -np.inf
+    return -res.fun
+
+
+def test_existence_matches_moment_cone(orc):
+    """The maximum-entropy equilibrium exists exactly when the target moments
+    lie in the interior of the cone of non-negative lattice distributions."""
+    c = orc.velocities().astype(np.float64)
+    cases = [((0.1, 0.0, 0.0), 0.1), ((0.0, 0.0, 0.0), 0.12), ((0.5, 0.0, 0.0), 0.5), ((1.0, 1.0, 0.0), 0.5),
+             ((1.9, 0.0, 0.0), 0.5), ((0.3, 0.0, 0.0), 0.2), ((1.5, 0.0, 0.0), 1.5)]
+    for u, T in cases:
+        m = _maxwellian_moments(1.0, np.asarray(u), T)
+        margin = _interior_margin(c, m)
+        feq, _, _, it = orc.equilibrium(1.0, u, T, tol=1e-12, maxit=200)
+        if margin > 1e-9:
+            assert it >= 0, (u, T, margin)
+        elif margin < 0:
+            assert it < 0, (u, T, margin)
+
+
+def _cubic_group():
+    mats = []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1, -1), repeat=3):
+            R = np.zeros((3, 3))
+            for r, (p, s) in enumerate(zip(perm, signs)):
+                R[r, p] = s
+            mats.append(R)
+    return mats
+
+
+def test_cubic_symmetry_and_density_scaling(orc):
+    c = orc.velocities()
+    index = {tuple(v): i for i, v in enumerate(c.tolist())}
+    u = np.array([0.31, -0.17, 0.08])
+    T = 0.52
+    f0, _, lam0, _ = orc.equilibrium(1.0, u, T, tol=1e-14)
+    group = _cubic_group()
+    assert len(group) == 48
+    for R in group:
+        fr, _, _, it = orc.equilibrium(1.0, R @ u, T, tol=1e-14)
+        assert it >= 0
+        for i, v in enumerate(c):
+            j = index[tuple((R @ v).astype(int))]
+            assert abs(fr[j] - f0[i]) <= 1e-13 * f0[i] + 1e-17
+    f3, _, lam3, _ = orc.equilibrium(3.7, u, T, tol=1e-14)
+    np.testing.assert_allclose(f3, 3.7 * f0, rtol=1e-13)
+    np.testing.assert_allclose(lam3, lam0, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("gamma", [1.4, 1.3, 5.0 / 3.0])
+def test_second_population_identity(orc, gamma):
+    u = [0.2, 0.1, -0.3]
+    T = 0.55
+    feq, geq, _, _ = orc.equilibrium(1.3, u, T, gamma=gamma, tol=1e-14)
+    delta = 2.0 / (gamma - 1.0) - 3.0
+    np.testing.assert_allclose(geq, delta * T * feq, rtol=1e-15, atol=1e-300)
+    # total energy of f^eq + g^eq is rho (|u|^2 + 2 C_v T)
+    c = orc.velocities().astype(np.float64)
+    e = (feq * (c ** 2).sum(1)).sum() + geq.sum()
+    assert abs(e - 1.3 * (np.dot(u, u) + 2.0 / (gamma - 1.0) * T)) < 1e-13
+
+
+def test_warm_start_converges_without_iterations(orc):
+    """The warm start of the Sec. 5 table: multipliers that already satisfy
+    the constraints need zero Newton updates."""
+    u = np.array([0.4, 0.0, 0.1])
+    feq, _, lam, it = orc.equilibrium(1.0, u, 0.5, tol=1e-13)
+    assert it > 0
+    feq2, _, lam2, it2 = orc.equilibrium(1.0, u, 0.5, lam=lam, tol=1e-13)
+    assert it2 == 0
+    np.testing.assert_array_equal(feq2, feq)
