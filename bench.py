@@ -1,0 +1,160 @@
+#!/usr/bin/env python3
+"""Throughput of the fused D3Q39 13-moment DDF-LBM step on one MI355X.
+
+Workload (default): periodic 128^3 compressible Taylor-Green vortex, Ma 0.5,
+Re 1600, gamma 1.4, FP64 storage and arithmetic (the plain FP64 GPU step).
+The same workload is also timed with FP32- and FP16-shifted storage and
+reported under "modes".  A step is one fused stream-and-collide launch over
+all cells (f and g).  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode fp64|fp32s|fp16s]
+                  [--n 128] [--no-modes] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+# algorithmic bytes per cell update: 78 populations read + written, 13
+# multipliers read + written
+BYTES_PER_CELL = {"fp64": 2 * 78 * 8 + 2 * 13 * 8, "fp32s": 2 * 78 * 4 + 2 * 13 * 4, "fp16s": 2 * 78 * 2 + 2 * 13 * 4}
+DTYPE = {"fp64": "f64", "fp32s": "f32 (fp32-shifted storage)", "fp16s": "f32 (fp16-shifted storage)"}
+
+
+def tgv_setup(n, ma=0.5, re=1600.0, gamma=1.4, T0=0.5):
+    from paper_1910_13515_amd import inputs
+    U = ma * math.sqrt(gamma * T0)
+    fields = inputs.taylor_green_fields(n, U, T0)
+    kw = dict(gamma=gamma, mach=ma, reynolds=re, length_ref=n / (2 * math.pi), T_ref=T0, u_dir=(1, 0, 0),
+              kn_relax=True)
+    return fields, kw
+
+
+def run_mode(mode, n, steps, warmup):
+    import torch
+    from paper_1910_13515_amd import lbm
+    fields, kw = tgv_setup(n)
+    s = lbm.Solver((n, n, n), fields=fields, storage=mode, **kw)
+    cells = n ** 3
+    s.step(warmup)
+    torch.cuda.synchronize()
+    stream = s.stream
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    s.step(steps)
+    end.record(stream)
+    end.synchronize()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    st = s.step(1, stats=True)  # statistics of one further step (not timed)
+    info = s.info()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    ms_step = ms / steps
+    glups = cells * steps / (ms * 1e-3) / 1e9
+    bytes_launch = BYTES_PER_CELL[mode] * cells
+    achieved = bytes_launch / (ms_step * 1e-3) / 1e9
+    return {
+        "glups": glups,
+        "ms_per_step": ms_step,
+        "tau": info.tau,
+        "newton_iterations_per_cell": st.iterations / max(1, st.cell_updates),
+        "newton_max_iterations": st.max_iterations,
+        "alpha_hist": list(st.alpha_hist),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_cell": BYTES_PER_CELL[mode], "cells_per_launch": cells},
+    }
+
+
+def cpu_baseline(seconds_target=15.0):
+    """The FP64 oracle on the host cores: TGV 32^3 (same Ma, Re), a bounded
+    number of steps.  Reported in GLUPS."""
+    import oracle
+    n = 32
+    fields, kw = tgv_setup(n)
+    # relaxation time with the same model viscosity as the GPU run
+    U = kw["mach"] * math.sqrt(kw["gamma"] * kw["T_ref"])
+    tau = oracle.tau_from_reynolds(U, kw["length_ref"], kw["reynolds"], kw["T_ref"])
+    o = oracle.Oracle(n, n, n, gamma=kw["gamma"], tau=tau, kn_relax=True, newton_tol=1e-12, newton_maxit=20)
+    o.init(*fields)
+    t0 = time.perf_counter()
+    steps = 0
+    while time.perf_counter() - t0 < seconds_target or steps < 1:
+        o.step(1)
+        steps += 1
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n ** 3 * steps / dt / 1e9, "unit": "GLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle, TGV {n}^3 Ma 0.5 Re 1600, {steps} steps from the initial state, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32s", "fp16s"])
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--no-modes", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the single-domain path is not sharded across GPUs "
+              "(see the multi-GPU design notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    from paper_1910_13515_amd import lbm
+    lbm.load()
+
+    main_res = run_mode(args.mode, args.n, args.steps, args.warmup)
+    print(f"# {args.mode}: {main_res['glups']:.3f} GLUPS, {main_res['ms_per_step']:.3f} ms/step", file=sys.stderr,
+          flush=True)
+    modes = {}
+    if not args.no_modes:
+        for m in ("fp64", "fp32s", "fp16s"):
+            if m == args.mode:
+                continue
+            r = run_mode(m, args.n, args.steps, args.warmup)
+            print(f"# {m}: {r['glups']:.3f} GLUPS, {r['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+            modes[m] = r
+    cpu = None if args.no_cpu else cpu_baseline()
+    roof = dict(main_res["roofline"])
+    out = {
+        "metric": "GLUPS (D3Q39 f+g cell updates per second)",
+        "value": main_res["glups"],
+        "unit": "GLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[args.mode],
+        "data": "synthetic (analytic Taylor-Green initial fields)",
+        "config": {"workload": f"periodic {args.n}^3 compressible Taylor-Green vortex, Ma 0.5, Re 1600, "
+                               f"gamma 1.4, {args.mode} step", "cells": args.n ** 3, "storage": args.mode,
+                   "tau": main_res["tau"], "newton_iterations_per_cell": main_res["newton_iterations_per_cell"],
+                   "alpha_hist": main_res["alpha_hist"]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "modes": modes,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,170 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) D3Q39 13-moment double-distribution
+ * lattice Boltzmann library.
+ *
+ * Method: Latt, Coreixas, Beny, Parmigiani, "Efficient supersonic flows
+ * through high-order guided equilibrium with lattice Boltzmann" (2019).
+ *   - lattice: Sec. 3, D3Q39 (E_{3,7}^{39});
+ *   - equilibrium: Sec. 2, Eq. (eq:discrete-equilibrium), the exponential of
+ *     13 monomials whose multipliers match the 13 Maxwell-Boltzmann moments of
+ *     Eq. (eq:13constraints), found by Newton-Raphson warm-started from the
+ *     previous step (Sec. 5, algorithm table);
+ *   - second population: Eq. (eq:discrete-equilibrium-poly);
+ *   - collide-and-stream with BGK for f and g, Pr = 1: Sec. 3;
+ *   - Knudsen-dependent relaxation time: Eq. (eq:DeltaAvg) and Eq. (eq:alpha);
+ *   - boundary conditions of the NACA0012 set-up (Sec. 4): free-stream
+ *     equilibrium faces, first-order Neumann outlet, half-way bounce-back.
+ *
+ * Conventions shared by every call:
+ *   - All functions return an lbm_status (0 = success, negative = error) or,
+ *     where stated, a non-negative count.  No C++ exception, abort or exit
+ *     crosses the ABI.  lbm_last_error() describes the last failure.
+ *   - Cells are numbered x fastest: cell = x + nx*(y + ny*z).  Host field
+ *     arrays are structure-of-arrays in that order.
+ *   - Velocity i of the lattice is returned by lbm_velocities(); for every odd
+ *     i, velocity i+1 is its opposite; velocity 0 is the rest velocity.
+ *   - Multiplier k multiplies basis function phi_k of the exponent, with
+ *     phi = (1, xi_x, xi_y, xi_z, xi_x^2, xi_y^2, xi_z^2, xi_x xi_y, xi_x xi_z,
+ *     xi_y xi_z, xi_x |xi|^2, xi_y |xi|^2, xi_z |xi|^2).
+ *   - Device memory is the caller's: lbm_create() sub-allocates everything it
+ *     needs inside a caller-provided device arena and never calls hipMalloc.
+ *     The arena must stay allocated until lbm_destroy().
+ *   - Work is enqueued on the caller's HIP stream (hipStream_t passed as
+ *     void*; NULL = the null stream).  Calls on one context are not
+ *     thread-safe; distinct contexts are independent.
+ */
+#ifndef LBM13_LBM_H
+#define LBM13_LBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_E_INVAL = -1,          /* invalid argument or parameter */
+    LBM_E_NOMEM = -2,          /* arena smaller than lbm_required_bytes() */
+    LBM_E_DEVICE = -3,         /* a HIP call failed, or the library was built for another GPU */
+    LBM_E_NONREALIZABLE = -4,  /* a reference or initial state has no 13-moment equilibrium */
+    LBM_E_NEWTON = -5,         /* at least one cell's Newton solve did not converge (state stays defined) */
+    LBM_E_NONFINITE = -6       /* a moment is NaN or infinite */
+} lbm_status;
+
+typedef enum {
+    LBM_STORE_FP64 = 0,          /* populations and multipliers in FP64, arithmetic in FP64 */
+    LBM_STORE_FP32_SHIFTED = 1,  /* populations stored in FP32 as deviations from shift weights, FP32 arithmetic */
+    LBM_STORE_FP16_SHIFTED = 2   /* deviations stored in FP16 (power-of-two scaled per velocity), FP32 arithmetic */
+} lbm_storage;
+
+typedef enum {
+    LBM_FACE_PERIODIC = 0,     /* wrap around (both faces of an axis must be periodic) */
+    LBM_FACE_EQUILIBRIUM = 1,  /* three outer layers frozen at the equilibrium of their initial state */
+    LBM_FACE_NEUMANN = 2       /* three outer layers read as copies of the nearest interior layer */
+} lbm_face;
+
+/* Problem statement.  Every field is read during lbm_create() only; the
+ * pointers may be freed afterwards.  Zero/NULL selects the default noted. */
+typedef struct {
+    int32_t nx, ny, nz;        /* cells (>= 1; a non-periodic axis needs >= 7) */
+    int32_t storage;           /* lbm_storage */
+    int32_t shift_ref;         /* shifted storage only: 0 = rest-state equilibrium at (rho_ref, T_ref),
+                                  1 = equilibrium of the reference stream (rho_ref, u_ref, T_ref) */
+    int32_t kn_relax;          /* 1: tau(eps) = tau * alpha(eps), Eq. (eq:alpha); 0: plain BGK */
+    int32_t newton_maxit;      /* cap on Newton updates per cell and step (0: 20) */
+    int32_t faces[6];          /* lbm_face for -x, +x, -y, +y, -z, +z */
+    double gamma;              /* heat-capacity ratio, 1 < gamma <= 5/3 (C_v = 1/(gamma-1), D = 3) */
+    double mach;               /* |u_ref| / sqrt(gamma T_ref) */
+    double reynolds;           /* |u_ref| L_ref / nu, nu = K(T_ref) (tau - 1/2) (used when tau <= 0) */
+    double length_ref;         /* L_ref in cells (used when tau <= 0) */
+    double rho_ref, T_ref;     /* reference (free-stream) state; 0 selects 1 and 0.5 */
+    double u_dir[3];           /* direction of u_ref (normalised here; zero vector with mach = 0 is allowed) */
+    double tau;                /* > 0: relaxation time as given; <= 0: derived from reynolds */
+    double newton_tol;         /* stopping bound on max_k |G_k|/rho relative to max(1, max_k |M_k|/rho)
+                                  (0: 1e-12 in FP64 as in Sec. 5, 2e-6 in FP32 arithmetic) */
+    const uint8_t *solid;      /* nx*ny*nz obstacle flags (nonzero = solid) or NULL */
+    const double *init_rho;    /* initial fields (N, 3N as ux|uy|uz, N) or NULL for the reference state */
+    const double *init_u;
+    const double *init_T;
+} lbm_params;
+
+/* Per-call statistics of lbm_step(), summed over fluid cells and steps. */
+typedef struct {
+    int64_t cell_updates;      /* fluid cells x steps */
+    int64_t iterations;        /* accepted Newton updates */
+    int64_t max_iterations;    /* largest count of one cell in one step */
+    int64_t failed;            /* cell-steps whose Newton did not converge */
+    int64_t cold_restarts;     /* cell-steps whose warm start failed and were restarted cold */
+    int64_t alpha_hist[4];     /* cell-steps per branch of Eq. (eq:alpha) */
+} lbm_step_stats;
+
+/* Values derived by lbm_create(). */
+typedef struct {
+    double tau;                /* relaxation time in use */
+    double u_ref[3];           /* reference velocity */
+    double shear_response;     /* K(T_ref): nu = K (tau - 1/2) */
+    double delta;              /* 2 C_v - D, the factor of g^eq = delta T f^eq */
+    int64_t cells;             /* nx*ny*nz */
+    int64_t fluid_cells;       /* cells updated by a step */
+    int64_t steps_done;        /* steps taken since creation or the last lbm_set_state() */
+    int64_t arena_bytes_used;
+} lbm_info;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int32_t lbm_version(void);
+
+/* Writes the 39 lattice velocities (39 x 3 int32, row i = velocity i). */
+int lbm_velocities(int32_t *out);
+
+/* Bytes of device arena that lbm_create() needs for these parameters, or a
+ * negative lbm_status if they are invalid.  This is the admission footprint. */
+int64_t lbm_required_bytes(const lbm_params *params);
+
+/* Validates the parameters, sub-allocates the arena (device pointer, 256-byte
+ * aligned, at least lbm_required_bytes()), uploads the obstacle and initial
+ * fields and writes the initial state: every cell at the equilibrium of its
+ * initial (rho, u, T), multipliers from a cold-started Newton solve.  Blocks
+ * until the initial state is written.  On success *out owns the context. */
+int lbm_create(const lbm_params *params, void *dev_arena, int64_t arena_bytes, void *hip_stream, lbm_ctx **out);
+
+/* Advances nsteps >= 0 time steps (fused pull-stream and collide, Sec. 3).
+ * Asynchronous on the stream when stats is NULL; otherwise synchronises and
+ * fills *stats.  Returns LBM_E_NEWTON if a cell failed to converge (counted in
+ * stats; the state stays defined, holding the last Newton iterate). */
+int lbm_step(lbm_ctx *ctx, int32_t nsteps, lbm_step_stats *stats);
+
+/* Macroscopic fields of the current state, in FP64.  out_host (nullable):
+ * 5*N doubles, SoA rho | ux | uy | uz | T; NaN at solid cells; Neumann
+ * boundary cells report the interior cell they copy.  totals (nullable):
+ * mass, momentum x, y, z and total energy (sum over i of (f_i |xi_i|^2 +
+ * g_i) / 2), summed over fluid cells in a fixed order.  Synchronises.  Returns
+ * LBM_E_NONFINITE if any fluid-cell moment is not finite. */
+int lbm_moments(lbm_ctx *ctx, double *out_host, double *totals);
+
+/* Copies the state to host FP64 arrays (each nullable): f and g as [39][N],
+ * multipliers as [13][N].  Shifted storage is decoded.  Synchronises. */
+int lbm_get_state(lbm_ctx *ctx, double *f, double *g, double *lam);
+
+/* Replaces the state (all three arrays required, layouts as above; shifted
+ * storage is encoded with rounding to nearest).  Writes both ping-pong
+ * buffers, so boundary and solid cells take the given values too.  Resets
+ * steps_done.  Synchronises. */
+int lbm_set_state(lbm_ctx *ctx, const double *f, const double *g, const double *lam);
+
+int lbm_get_info(const lbm_ctx *ctx, lbm_info *info);
+
+/* Releases the context (not the caller's arena).  Synchronises the stream. */
+int lbm_destroy(lbm_ctx *ctx);
+
+/* Message of the last failure on ctx, or of the calling thread's last failed
+ * call that had no context (ctx = NULL).  Never NULL. */
+const char *lbm_last_error(const lbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM13_LBM_H */

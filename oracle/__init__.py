@@ -29,6 +29,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lbm_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+# the same source built with fused multiply-add contraction: a second
+# rounding of the same arithmetic, used to measure how fast round-off
+# differences grow along a trajectory (the floor any other implementation
+# can be compared against)
+LIB_FMA = os.path.join(HERE, "liboracle_fma.so")
 
 NQ = 39
 NL = 13
@@ -38,12 +43,13 @@ CELL_FLUID, CELL_SOLID, CELL_FROZEN, CELL_NEUMANN = 0, 1, 2, 3
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP, no FMA contraction)."""
-    if force or not os.path.exists(LIB):
-        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-               "-o", LIB + ".tmp", SRC, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(LIB + ".tmp", LIB)
+    """Compile the oracle with gcc (-O2, OpenMP, no FMA contraction), and the
+    FMA-contracted variant."""
+    for out, extra in ((LIB, ["-ffp-contract=off"]), (LIB_FMA, ["-mfma", "-mavx2", "-ffp-contract=fast"])):
+        if force or not os.path.exists(out):
+            cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp"] + extra + ["-o", out + ".tmp", SRC, "-lm"]
+            subprocess.run(cmd, check=True)
+            os.replace(out + ".tmp", out)
     return LIB
 
 
@@ -65,15 +71,16 @@ class Stats(ctypes.Structure):
     ]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB):
-            build()
-        L = ctypes.CDLL(LIB)
+def lib(variant: str = "plain"):
+    """The compiled oracle; variant "fma" is the FMA-contracted build."""
+    if variant not in _libs:
+        path = LIB if variant == "plain" else LIB_FMA
+        if not os.path.exists(path):
+            build(force=False)
+        L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         L.orc_equilibrium.restype = ctypes.c_int
         L.orc_equilibrium.argtypes = [ctypes.c_double, dp, ctypes.c_double, ctypes.c_double, dp, ctypes.c_int,
@@ -82,8 +89,8 @@ def lib():
         L.orc_step.restype = None
         L.orc_moments.restype = None
         L.orc_stream_only.restype = None
-        _lib = L
-    return _lib
+        _libs[variant] = L
+    return _libs[variant]
 
 
 def _ptr(a):
@@ -114,11 +121,22 @@ def equilibrium(rho, u, T, gamma=1.4, lam=None, tol=1e-13, maxit=100):
     return feq, geq, lam, it
 
 
+def shear_response(T: float, du: float = 1e-4) -> float:
+    """K(T) = d/du_y sum_i f^eq_i xi_x^2 xi_y at rest, per unit density, by a
+    central difference of this oracle's equilibrium.  The BGK lattice step has
+    shear viscosity nu = K (tau - 1/2); the continuous Maxwellian would give
+    K = T, but the 13 constraints fix only the contracted third moment."""
+    c = velocities().astype(np.float64)
+    fp, _, _, _ = equilibrium(1.0, [0.0, du, 0.0], T, tol=1e-15)
+    fm, _, _, _ = equilibrium(1.0, [0.0, -du, 0.0], T, tol=1e-15)
+    return float(((fp - fm) * c[:, 0] ** 2 * c[:, 1]).sum() / (2.0 * du))
+
+
 def tau_from_reynolds(speed: float, length: float, reynolds: float, T_ref: float) -> float:
     """Relaxation time for a Reynolds number.  Reading (the paper is silent):
-    BGK Chapman-Enskog kinematic viscosity nu = T (tau - 1/2) in lattice units,
-    so tau = 1/2 + |u| L / (Re T)."""
-    return 0.5 + speed * length / (reynolds * T_ref)
+    Re = |u| L / nu with the model's own shear viscosity nu = K(T_ref)
+    (tau - 1/2), so tau = 1/2 + |u| L / (Re K)."""
+    return 0.5 + speed * length / (reynolds * shear_response(T_ref))
 
 
 class Oracle:
@@ -126,7 +144,8 @@ class Oracle:
     multipliers lam, SoA ``[39][N]`` / ``[13][N]`` with x fastest)."""
 
     def __init__(self, nx, ny, nz, gamma=1.4, tau=0.6, kn_relax=True, faces=(0,) * 6, solid=None,
-                 newton_tol=1e-13, newton_maxit=30):
+                 newton_tol=1e-13, newton_maxit=30, variant="plain"):
+        self.L = lib(variant)
         self.shape = (nx, ny, nz)
         self.n = nx * ny * nz
         self.gamma = float(gamma)
@@ -156,7 +175,7 @@ class Oracle:
         u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
         T = np.ascontiguousarray(T, dtype=np.float64).reshape(-1)
         assert rho.size == self.n and u.size == 3 * self.n and T.size == self.n
-        return int(lib().orc_init(ctypes.byref(self.p), _ptr(rho), _ptr(u), _ptr(T), _ptr(self.f), _ptr(self.g),
+        return int(self.L.orc_init(ctypes.byref(self.p), _ptr(rho), _ptr(u), _ptr(T), _ptr(self.f), _ptr(self.g),
                                   _ptr(self.lam)))
 
     def set_state(self, f, g, lam):
@@ -174,7 +193,7 @@ class Oracle:
         tot = Stats()
         for _ in range(nsteps):
             st = Stats()
-            lib().orc_step(ctypes.byref(self.p), _ptr(self.f), _ptr(self.g), _ptr(self.lam), _ptr(fo), _ptr(go),
+            self.L.orc_step(ctypes.byref(self.p), _ptr(self.f), _ptr(self.g), _ptr(self.lam), _ptr(fo), _ptr(go),
                            _ptr(lo), _ptr(iters), _ptr(eps), ctypes.byref(st))
             self.f, fo = fo, self.f
             self.g, go = go, self.g
@@ -193,16 +212,16 @@ class Oracle:
     def stream_only(self, h):
         h = np.ascontiguousarray(h, dtype=np.float64).reshape(-1)
         out = np.empty_like(h)
-        lib().orc_stream_only(ctypes.byref(self.p), _ptr(h), _ptr(out))
+        self.L.orc_stream_only(ctypes.byref(self.p), _ptr(h), _ptr(out))
         return out
 
     def moments(self):
         out = np.empty(5 * self.n)
         tot = np.empty(5)
-        lib().orc_moments(ctypes.byref(self.p), _ptr(self.f), _ptr(self.g), _ptr(out), _ptr(tot))
+        self.L.orc_moments(ctypes.byref(self.p), _ptr(self.f), _ptr(self.g), _ptr(out), _ptr(tot))
         return out.reshape(5, self.n), tot
 
     def cell_types(self):
         out = np.empty(self.n, dtype=np.uint8)
-        lib().orc_cell_types(ctypes.byref(self.p), _ptr(out))
+        self.L.orc_cell_types(ctypes.byref(self.p), _ptr(out))
         return out

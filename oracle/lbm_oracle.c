@@ -427,10 +427,12 @@ static int64_t pull_source(const orc_params *p, int x, int y, int z, int i, int 
         }
     }
     {
+        /* Reading of the Neumann rule: a coordinate inside a Neumann face's
+         * three layers reads the nearest interior layer along that face's
+         * normal, also where the layer meets another face. */
         int s[3];
         for (a = 0; a < 3; ++a) s[a] = step_axis(p, a, c[a], -VEL[i][a]);
-        if (cell_type(p, s[0], s[1], s[2]) == CELL_NEUMANN) return neumann_source(p, s[0], s[1], s[2]);
-        return cell_index(p, s[0], s[1], s[2]);
+        return neumann_source(p, s[0], s[1], s[2]);
     }
 }
 

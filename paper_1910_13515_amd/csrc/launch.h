@@ -1,0 +1,28 @@
+// Launch wrappers of the device kernels (internal C++ interface between the
+// kernel translation unit and the C ABI layer).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "slot.h"
+
+namespace lbm13 {
+
+hipError_t launch_step(int storage, const SlotTable *tab, int grid, int j, int64_t *stats, hipStream_t st);
+const void *step_kernel_symbol(int storage);
+hipError_t launch_init(int storage, const SlotDesc &d, const double *fields, unsigned long long *failed,
+                       hipStream_t st);
+hipError_t launch_single_equilibrium(double rho, const double u[3], double T, double tol, int maxit, double *out,
+                                     int *status, hipStream_t st);
+hipError_t launch_moments(int storage, const SlotDesc &d, int parity, double *out, double *partial, double *totals,
+                          hipStream_t st);
+int moments_partial_blocks(int64_t n);
+hipError_t launch_zero(int64_t *p, int64_t count, hipStream_t st);
+hipError_t launch_reduce_stats(const int64_t *partial, int nwaves, int64_t *out, hipStream_t st);
+hipError_t launch_decode_pop(int storage, const SlotDesc &d, int parity, int pop, double *out, hipStream_t st);
+hipError_t launch_encode_pop(int storage, const SlotDesc &d, int pop, const double *in, hipStream_t st);
+hipError_t launch_copy_lam(int storage, const SlotDesc &d, int k, int to_device, double *host_side, hipStream_t st);
+
+}  // namespace lbm13

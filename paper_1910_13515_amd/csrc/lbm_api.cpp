@@ -1,0 +1,594 @@
+// C ABI of the D3Q39 13-moment DDF lattice Boltzmann library (declared in
+// include/lbm.h).  Host side: parameter validation, derived constants, arena
+// layout, obstacle link masks, and the launch sequences of the device kernels.
+#include "lbm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "d3q39.h"
+#include "launch.h"
+#include "slot.h"
+
+using namespace lbm13;
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+constexpr int64_t kAlign = 256;
+constexpr int kMaxGrid = 2048;  // persistent grid cap (blocks); sizes the statistics partials
+
+int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int64_t storage_bytes(int storage) { return storage == kStoreF64 ? 8 : storage == kStoreF32 ? 4 : 2; }
+int64_t lam_bytes(int storage) { return storage == kStoreF64 ? 8 : 4; }
+
+struct Layout {
+    int64_t buf[2], lam, links, fields, partial, totals, stats, stat_out, failed, table, single, single_status;
+    int64_t total;
+};
+
+Layout make_layout(const lbm_params &p)
+{
+    const int64_t n = (int64_t)p.nx * p.ny * p.nz;
+    Layout L{};
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        const int64_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    const int64_t pop_bytes = 2LL * kQ * n * storage_bytes(p.storage);
+    L.buf[0] = take(pop_bytes);
+    L.buf[1] = take(pop_bytes);
+    L.lam = take((int64_t)kM * n * lam_bytes(p.storage));
+    L.links = p.solid ? take(n * 8) : -1;
+    L.fields = take(5 * n * 8);
+    L.partial = take((int64_t)moments_partial_blocks(n) * 5 * 8);
+    L.totals = take(5 * 8);
+    L.stats = take((int64_t)kMaxGrid * kWavesPerBlock * kStatWords * 8);
+    L.stat_out = take(kStatWords * 8);
+    L.failed = take(8);
+    L.table = take((int64_t)slot_table_bytes(1));
+    L.single = take((kQ + kM) * 8);
+    L.single_status = take(8);
+    L.total = off;
+    return L;
+}
+
+bool face_ok(int f) { return f == LBM_FACE_PERIODIC || f == LBM_FACE_EQUILIBRIUM || f == LBM_FACE_NEUMANN; }
+
+// Returns an empty string when the parameters are acceptable.
+std::string validate(const lbm_params *p)
+{
+    if (!p) return "params is NULL";
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return "grid dimensions must be >= 1";
+    const int64_t n = (int64_t)p->nx * p->ny * p->nz;
+    if (n > (int64_t)1 << 40) return "grid too large";
+    if (p->storage < LBM_STORE_FP64 || p->storage > LBM_STORE_FP16_SHIFTED) return "unknown storage mode";
+    if (p->shift_ref < 0 || p->shift_ref > 1) return "shift_ref must be 0 or 1";
+    const int dims[3] = {p->nx, p->ny, p->nz};
+    for (int a = 0; a < 3; ++a) {
+        const int lo = p->faces[2 * a], hi = p->faces[2 * a + 1];
+        if (!face_ok(lo) || !face_ok(hi)) return "unknown face kind";
+        if ((lo == LBM_FACE_PERIODIC) != (hi == LBM_FACE_PERIODIC))
+            return "both faces of an axis must be periodic, or neither";
+        if (lo != LBM_FACE_PERIODIC && dims[a] < 7) return "a non-periodic axis needs at least 7 cells";
+    }
+    if (!(p->gamma > 1.0 && p->gamma <= 5.0 / 3.0 + 1e-12)) return "gamma must satisfy 1 < gamma <= 5/3";
+    if (!(p->mach >= 0.0) || !std::isfinite(p->mach)) return "mach must be finite and >= 0";
+    if (!(p->rho_ref >= 0.0) || !(p->T_ref >= 0.0)) return "rho_ref and T_ref must be >= 0";
+    if (!std::isfinite(p->tau)) return "tau must be finite";
+    if (p->tau > 0.0 && p->tau < 0.5) return "tau must be >= 1/2";
+    if (p->tau <= 0.0 && !(p->reynolds > 0.0 && p->length_ref > 0.0 && p->mach > 0.0))
+        return "tau <= 0 needs reynolds > 0, length_ref > 0 and mach > 0";
+    if (p->newton_maxit < 0 || p->newton_maxit > 1000) return "newton_maxit out of range";
+    if (!(p->newton_tol >= 0.0) || !std::isfinite(p->newton_tol)) return "newton_tol must be finite and >= 0";
+    if (p->mach > 0.0) {
+        const double du = std::sqrt(p->u_dir[0] * p->u_dir[0] + p->u_dir[1] * p->u_dir[1] + p->u_dir[2] * p->u_dir[2]);
+        if (!(du > 0.0) || !std::isfinite(du)) return "u_dir must be a nonzero finite vector when mach > 0";
+    }
+    if ((p->init_rho != nullptr) != (p->init_u != nullptr) || (p->init_rho != nullptr) != (p->init_T != nullptr))
+        return "init_rho, init_u and init_T must be all given or all NULL";
+    return "";
+}
+
+double pow2_near(double x)
+{
+    if (!(x > 0.0) || !std::isfinite(x)) return 1.0;
+    return std::ldexp(1.0, (int)std::lround(std::log2(x)));
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_params params{};
+    Layout layout{};
+    hipStream_t stream = nullptr;
+    char *arena = nullptr;
+    int storage = 0;
+    SlotDesc desc{};
+    SlotTable *d_table = nullptr;
+    int grid = 8;
+    int64_t steps = 0;
+    int64_t fluid_cells = 0;
+    double tau = 0.0, shear_response = 0.0, u_ref[3] = {0, 0, 0};
+    std::string err = "no error";
+};
+
+namespace {
+
+int fail(lbm_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    else g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                              \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess)                                                                           \
+            return fail(ctx, LBM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));          \
+    } while (0)
+
+template <class T>
+T *at(char *arena, int64_t off)
+{
+    return reinterpret_cast<T *>(arena + off);
+}
+
+// Equilibrium of one state on the device (FP64), copied to host.
+int device_equilibrium(lbm_ctx *c, double rho, const double u[3], double T, double out[kQ + kM])
+{
+    double *d_out = at<double>(c->arena, c->layout.single);
+    int *d_st = at<int>(c->arena, c->layout.single_status);
+    HIP_TRY(c, launch_single_equilibrium(rho, u, T, 1e-14, 200, d_out, d_st, c->stream));
+    int st = 0;
+    HIP_TRY(c, hipMemcpyAsync(out, d_out, sizeof(double) * (kQ + kM), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(&st, d_st, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (st == kFailed) return fail(c, LBM_E_NONREALIZABLE, "reference state has no 13-moment equilibrium");
+    return LBM_OK;
+}
+
+// Shear response K(T) of the rest-state equilibrium w (per unit density):
+// the linear response of the equilibrium to u_y at rest is w_i (a xi_y +
+// b xi_y |xi|^2), with (a, b) solving the 2x2 block of J for the targets'
+// derivatives (1, (D+2) T); K = sum_i that response times xi_x^2 xi_y.
+double shear_response(const double *w, double T)
+{
+    double j11 = 0, j12 = 0, j22 = 0, k1 = 0, k2 = 0;
+    for (int i = 0; i < kQ; ++i) {
+        const double cx = vel(i, 0), cy = vel(i, 1), cz = vel(i, 2);
+        const double q = cx * cx + cy * cy + cz * cz;
+        j11 += w[i] * cy * cy;
+        j12 += w[i] * cy * cy * q;
+        j22 += w[i] * cy * cy * q * q;
+        k1 += w[i] * cx * cx * cy * cy;
+        k2 += w[i] * cx * cx * cy * cy * q;
+    }
+    const double r1 = 1.0, r2 = 5.0 * T;
+    const double det = j11 * j22 - j12 * j12;
+    const double a = (r1 * j22 - j12 * r2) / det;
+    const double b = (j11 * r2 - j12 * r1) / det;
+    return a * k1 + b * k2;
+}
+
+// Per-cell link mask for half-way bounce-back: bit i set when a lattice node
+// passed over by velocity i (x - k dir_i, k = 1..mult_i) is solid; bit 63 for
+// solid cells.  Computed for fluid cells only.
+void build_links(const lbm_params &p, std::vector<uint64_t> &links)
+{
+    const int64_t nx = p.nx, ny = p.ny, nz = p.nz, n = nx * ny * nz;
+    links.assign(n, 0);
+    const int dims[3] = {p.nx, p.ny, p.nz};
+    bool periodic[3];
+    for (int a = 0; a < 3; ++a) periodic[a] = p.faces[2 * a] == LBM_FACE_PERIODIC;
+    auto wrap = [&](int v, int a) {
+        if (!periodic[a]) return v;
+        const int m = dims[a];
+        v %= m;
+        return v < 0 ? v + m : v;
+    };
+    auto fluid_coord = [&](int x, int y, int z) {
+        const int c[3] = {x, y, z};
+        for (int a = 0; a < 3; ++a)
+            if (!periodic[a] && (c[a] < 3 || c[a] >= dims[a] - 3)) return false;
+        return true;
+    };
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const int64_t cell = x + nx * (y + ny * (int64_t)z);
+                if (p.solid[cell]) {
+                    links[cell] = 1ull << 63;
+                    continue;
+                }
+                if (!fluid_coord(x, y, z)) continue;
+                uint64_t m = 0;
+                for (int i = 1; i < kQ; ++i) {
+                    const int c[3] = {vel(i, 0), vel(i, 1), vel(i, 2)};
+                    const int mult = std::max({std::abs(c[0]), std::abs(c[1]), std::abs(c[2])});
+                    for (int k = 1; k <= mult; ++k) {
+                        const int sx = wrap(x - k * (c[0] / mult), 0);
+                        const int sy = wrap(y - k * (c[1] / mult), 1);
+                        const int sz = wrap(z - k * (c[2] / mult), 2);
+                        if (p.solid[sx + nx * (sy + ny * (int64_t)sz)]) {
+                            m |= 1ull << i;
+                            break;
+                        }
+                    }
+                }
+                links[cell] = m;
+            }
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t lbm_version(void) { return 10000; }
+
+int lbm_velocities(int32_t *out)
+{
+    if (!out) return fail(nullptr, LBM_E_INVAL, "out is NULL");
+    for (int i = 0; i < kQ; ++i)
+        for (int a = 0; a < 3; ++a) out[3 * i + a] = vel(i, a);
+    return LBM_OK;
+}
+
+int64_t lbm_required_bytes(const lbm_params *params)
+{
+    const std::string v = validate(params);
+    if (!v.empty()) return fail(nullptr, LBM_E_INVAL, v);
+    return make_layout(*params).total;
+}
+
+int lbm_create(const lbm_params *params, void *dev_arena, int64_t arena_bytes, void *hip_stream, lbm_ctx **out)
+{
+    if (!out) return fail(nullptr, LBM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    const std::string v = validate(params);
+    if (!v.empty()) return fail(nullptr, LBM_E_INVAL, v);
+    if (!dev_arena) return fail(nullptr, LBM_E_INVAL, "dev_arena is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_arena) % kAlign != 0)
+        return fail(nullptr, LBM_E_INVAL, "dev_arena must be 256-byte aligned");
+    const Layout L = make_layout(*params);
+    if (arena_bytes < L.total)
+        return fail(nullptr, LBM_E_NOMEM,
+                    "arena of " + std::to_string(arena_bytes) + " bytes < required " + std::to_string(L.total));
+
+    {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+            return fail(nullptr, LBM_E_DEVICE, "no HIP device");
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            return fail(nullptr, LBM_E_DEVICE, std::string("library built for gfx950, device is ") + prop.gcnArchName);
+    }
+
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(nullptr, LBM_E_NOMEM, "host allocation failed");
+    c->params = *params;
+    c->params.solid = nullptr;
+    c->params.init_rho = c->params.init_u = c->params.init_T = nullptr;
+    c->layout = L;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->arena = static_cast<char *>(dev_arena);
+    c->storage = params->storage;
+    lbm_params &p = c->params;
+    if (p.rho_ref == 0.0) p.rho_ref = 1.0;
+    if (p.T_ref == 0.0) p.T_ref = 0.5;
+    if (p.newton_maxit == 0) p.newton_maxit = 20;
+    if (p.newton_tol == 0.0) p.newton_tol = p.storage == LBM_STORE_FP64 ? 1e-12 : 2e-6;
+
+    auto bail = [&](int code) {
+        g_last_error = c->err;
+        delete c;
+        return code;
+    };
+
+    const double Cv = 1.0 / (p.gamma - 1.0);
+    const double delta = 2.0 * Cv - 3.0;
+    const double cs = std::sqrt(p.gamma * p.T_ref);
+    if (p.mach > 0.0) {
+        const double du = std::sqrt(p.u_dir[0] * p.u_dir[0] + p.u_dir[1] * p.u_dir[1] + p.u_dir[2] * p.u_dir[2]);
+        for (int a = 0; a < 3; ++a) c->u_ref[a] = p.mach * cs * p.u_dir[a] / du;
+    }
+
+    // rest-state equilibrium at T_ref (shear response, rest shift weights)
+    double rest[kQ + kM], stream_eq[kQ + kM];
+    const double zero[3] = {0.0, 0.0, 0.0};
+    int rc = device_equilibrium(c, 1.0, zero, p.T_ref, rest);
+    if (rc != LBM_OK) return bail(rc);
+    rc = device_equilibrium(c, p.rho_ref, c->u_ref, p.T_ref, stream_eq);
+    if (rc != LBM_OK) return bail(rc);
+    c->shear_response = shear_response(rest, p.T_ref);
+
+    if (p.tau > 0.0) {
+        c->tau = p.tau;
+    } else {
+        const double speed = p.mach * cs;
+        c->tau = 0.5 + speed * p.length_ref / (p.reynolds * c->shear_response);
+    }
+
+    SlotDesc &d = c->desc;
+    std::memset(&d, 0, sizeof(d));
+    d.nx = p.nx;
+    d.ny = p.ny;
+    d.nz = p.nz;
+    d.nsegx = (p.nx + kSegment - 1) / kSegment;
+    d.n = (int64_t)p.nx * p.ny * p.nz;
+    d.segments = (int64_t)d.nsegx * p.ny * p.nz;
+    d.blocks = (int32_t)((d.segments + kWavesPerBlock - 1) / kWavesPerBlock);
+    for (int a = 0; a < 3; ++a) {
+        const int lo = p.faces[2 * a], hi = p.faces[2 * a + 1];
+        d.axis[a] = lo == LBM_FACE_PERIODIC ? kAxisPeriodic : kAxisOpen;
+        d.open_lo[a] = lo != LBM_FACE_PERIODIC;
+        d.open_hi[a] = hi != LBM_FACE_PERIODIC;
+        d.neumann_lo[a] = lo == LBM_FACE_NEUMANN;
+        d.neumann_hi[a] = hi == LBM_FACE_NEUMANN;
+    }
+    d.has_links = params->solid != nullptr;
+    d.kn_relax = p.kn_relax ? 1 : 0;
+    d.maxit = p.newton_maxit;
+    d.maxit_cold = std::max(p.newton_maxit, 100);
+    d.parity0 = 0;
+    d.steps_todo = 0x7fffffff;
+    d.storage = p.storage;
+    d.tol = p.newton_tol;
+    {
+        const double t1 = c->tau * 1.05, t2 = c->tau * 1.35;
+        d.omega[0] = 1.0 / c->tau;
+        d.omega[1] = 1.0 / t1;
+        d.omega[2] = 1.0 / t2;
+        d.omega[3] = 1.0;  // alpha = 1/tau: the cell is replaced by its equilibrium
+    }
+    d.delta = delta;
+    d.two_cv = 2.0 * Cv;
+    d.buf[0] = c->arena + L.buf[0];
+    d.buf[1] = c->arena + L.buf[1];
+    d.lam = c->arena + L.lam;
+    d.links = params->solid ? at<uint64_t>(c->arena, L.links) : nullptr;
+    d.stats = at<int64_t>(c->arena, L.stats);
+    if (p.storage != LBM_STORE_FP64) {
+        double w[2 * kQ];
+        for (int i = 0; i < kQ; ++i) {
+            w[i] = p.shift_ref ? stream_eq[i] : p.rho_ref * rest[i];
+            w[kQ + i] = delta * p.T_ref * w[i];
+        }
+        double mass = 0, mom[3] = {0, 0, 0}, ener = 0;
+        for (int i = 0; i < 2 * kQ; ++i) {
+            d.shift_w[i] = (float)w[i];
+            const double sc = p.storage == LBM_STORE_FP16_SHIFTED ? pow2_near(w[i] > 0 ? w[i] : w[i % kQ]) : 1.0;
+            d.shift_scale[i] = (float)sc;
+            d.shift_inv_scale[i] = (float)(1.0 / sc);
+        }
+        for (int i = 0; i < kQ; ++i) {
+            const double wf = (double)d.shift_w[i], wg = (double)d.shift_w[kQ + i];
+            const int cx = vel(i, 0), cy = vel(i, 1), cz = vel(i, 2);
+            mass += wf;
+            mom[0] += wf * cx;
+            mom[1] += wf * cy;
+            mom[2] += wf * cz;
+            ener += wf * (cx * cx + cy * cy + cz * cz) + wg;
+        }
+        d.ref_mass = (float)mass;
+        d.ref_mom[0] = (float)mom[0];
+        d.ref_mom[1] = (float)mom[1];
+        d.ref_mom[2] = (float)mom[2];
+        d.ref_energy = (float)ener;
+    }
+
+    // obstacle links
+    const int64_t n = d.n;
+    if (params->solid) {
+        std::vector<uint64_t> links;
+        build_links(*params, links);
+        HIP_TRY(c, hipMemcpyAsync(at<uint64_t>(c->arena, L.links), links.data(), n * 8, hipMemcpyHostToDevice,
+                                  c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    {
+        int64_t fluid = 0;
+        for (int64_t z = 0; z < p.nz; ++z)
+            for (int64_t y = 0; y < p.ny; ++y)
+                for (int64_t x = 0; x < p.nx; ++x) {
+                    const int64_t cc[3] = {x, y, z};
+                    const int64_t dims[3] = {p.nx, p.ny, p.nz};
+                    bool f = !(params->solid && params->solid[x + p.nx * (y + p.ny * z)]);
+                    for (int a = 0; a < 3 && f; ++a)
+                        if (d.open_lo[a] && (cc[a] < 3 || cc[a] >= dims[a] - 3)) f = false;
+                    fluid += f;
+                }
+        c->fluid_cells = fluid;
+    }
+
+    // initial fields -> equilibrium state
+    {
+        std::vector<double> host(5 * n);
+        for (int64_t i = 0; i < n; ++i) {
+            host[i] = params->init_rho ? params->init_rho[i] : p.rho_ref;
+            host[n + i] = params->init_u ? params->init_u[i] : c->u_ref[0];
+            host[2 * n + i] = params->init_u ? params->init_u[n + i] : c->u_ref[1];
+            host[3 * n + i] = params->init_u ? params->init_u[2 * n + i] : c->u_ref[2];
+            host[4 * n + i] = params->init_T ? params->init_T[i] : p.T_ref;
+        }
+        for (int64_t i = 0; i < n; ++i)
+            if (!(host[i] > 0.0) || !(host[4 * n + i] > 0.0) || !std::isfinite(host[i] + host[n + i] + host[2 * n + i] +
+                                                                                 host[3 * n + i] + host[4 * n + i])) {
+                c->err = "initial fields need finite values with rho > 0 and T > 0";
+                return bail(LBM_E_INVAL);
+            }
+        double *d_fields = at<double>(c->arena, L.fields);
+        unsigned long long *d_failed = at<unsigned long long>(c->arena, L.failed);
+        HIP_TRY(c, hipMemcpyAsync(d_fields, host.data(), 5 * n * 8, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemsetAsync(d_failed, 0, 8, c->stream));
+        SlotDesc di = d;
+        // the initial equilibrium is always solved in FP64 to the FP64 bound
+        di.tol = p.storage == LBM_STORE_FP64 ? p.newton_tol : 1e-12;
+        HIP_TRY(c, launch_init(p.storage, di, d_fields, d_failed, c->stream));
+        unsigned long long failed = 0;
+        HIP_TRY(c, hipMemcpyAsync(&failed, d_failed, 8, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (failed) {
+            c->err = std::to_string(failed) + " initial cells have no 13-moment equilibrium";
+            return bail(LBM_E_NONREALIZABLE);
+        }
+    }
+
+    // slot table (one slot) and persistent grid
+    {
+        std::vector<char> tab(slot_table_bytes(1), 0);
+        SlotTable *t = reinterpret_cast<SlotTable *>(tab.data());
+        t->nslots = 1;
+        t->total_blocks = d.blocks;
+        t->block_start[0] = 0;
+        t->block_start[1] = d.blocks;
+        t->slot[0] = d;
+        c->d_table = at<SlotTable>(c->arena, L.table);
+        HIP_TRY(c, hipMemcpyAsync(c->d_table, tab.data(), tab.size(), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        int dev = 0, per_cu = 1;
+        hipDeviceProp_t prop;
+        HIP_TRY(c, hipGetDevice(&dev));
+        HIP_TRY(c, hipGetDeviceProperties(&prop, dev));
+        HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step_kernel_symbol(p.storage),
+                                                                 kBlockThreads, 0));
+        int grid = std::max(1, per_cu) * prop.multiProcessorCount;
+        const int need = (d.blocks + 7) / 8 * 8;
+        grid = std::min(grid, need);
+        grid = std::min(grid, kMaxGrid);
+        grid = std::max(8, grid / 8 * 8);
+        c->grid = grid;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx *c, int32_t nsteps, lbm_step_stats *stats)
+{
+    if (!c) return fail(nullptr, LBM_E_INVAL, "ctx is NULL");
+    if (nsteps < 0) return fail(c, LBM_E_INVAL, "nsteps must be >= 0");
+    int64_t *d_stats = at<int64_t>(c->arena, c->layout.stats);
+    const int nwaves = c->grid * kWavesPerBlock;
+    if (stats) HIP_TRY(c, launch_zero(d_stats, (int64_t)nwaves * kStatWords, c->stream));
+    for (int32_t s = 0; s < nsteps; ++s) {
+        const int j = (int)((c->steps + s) & 1);
+        HIP_TRY(c, launch_step(c->storage, c->d_table, c->grid, j, d_stats, c->stream));
+    }
+    c->steps += nsteps;
+    if (!stats) return LBM_OK;
+    int64_t *d_out = at<int64_t>(c->arena, c->layout.stat_out);
+    HIP_TRY(c, launch_reduce_stats(d_stats, nwaves, d_out, c->stream));
+    int64_t h[kStatWords];
+    HIP_TRY(c, hipMemcpyAsync(h, d_out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    stats->cell_updates = c->fluid_cells * (int64_t)nsteps;
+    stats->iterations = h[0];
+    stats->max_iterations = h[1];
+    stats->failed = h[2];
+    stats->cold_restarts = h[3];
+    for (int k = 0; k < 4; ++k) stats->alpha_hist[k] = h[4 + k];
+    if (h[2] > 0) return fail(c, LBM_E_NEWTON, std::to_string(h[2]) + " cell updates did not converge");
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx *c, double *out_host, double *totals)
+{
+    if (!c) return fail(nullptr, LBM_E_INVAL, "ctx is NULL");
+    const int64_t n = c->desc.n;
+    double *d_fields = at<double>(c->arena, c->layout.fields);
+    double *d_partial = at<double>(c->arena, c->layout.partial);
+    double *d_totals = at<double>(c->arena, c->layout.totals);
+    HIP_TRY(c, launch_moments(c->storage, c->desc, (int)(c->steps & 1), d_fields, d_partial, d_totals, c->stream));
+    double t[5];
+    if (out_host) HIP_TRY(c, hipMemcpyAsync(out_host, d_fields, 5 * n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(t, d_totals, sizeof(t), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (totals)
+        for (int k = 0; k < 5; ++k) totals[k] = t[k];
+    for (int k = 0; k < 5; ++k)
+        if (!std::isfinite(t[k])) return fail(c, LBM_E_NONFINITE, "non-finite moments in fluid cells");
+    return LBM_OK;
+}
+
+int lbm_get_state(lbm_ctx *c, double *f, double *g, double *lam)
+{
+    if (!c) return fail(nullptr, LBM_E_INVAL, "ctx is NULL");
+    const int64_t n = c->desc.n;
+    double *d_fields = at<double>(c->arena, c->layout.fields);
+    const int parity = (int)(c->steps & 1);
+    for (int pop = 0; pop < 2 * kQ; ++pop) {
+        double *dst = pop < kQ ? f : g;
+        if (!dst) continue;
+        HIP_TRY(c, launch_decode_pop(c->storage, c->desc, parity, pop, d_fields, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(dst + (int64_t)(pop % kQ) * n, d_fields, n * 8, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    if (lam) {
+        for (int k = 0; k < kM; ++k) {
+            HIP_TRY(c, launch_copy_lam(c->storage, c->desc, k, 0, d_fields, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(lam + (int64_t)k * n, d_fields, n * 8, hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_set_state(lbm_ctx *c, const double *f, const double *g, const double *lam)
+{
+    if (!c) return fail(nullptr, LBM_E_INVAL, "ctx is NULL");
+    if (!f || !g || !lam) return fail(c, LBM_E_INVAL, "f, g and lam are required");
+    const int64_t n = c->desc.n;
+    double *d_fields = at<double>(c->arena, c->layout.fields);
+    for (int pop = 0; pop < 2 * kQ; ++pop) {
+        const double *srcp = (pop < kQ ? f : g) + (int64_t)(pop % kQ) * n;
+        HIP_TRY(c, hipMemcpyAsync(d_fields, srcp, n * 8, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, launch_encode_pop(c->storage, c->desc, pop, d_fields, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    for (int k = 0; k < kM; ++k) {
+        HIP_TRY(c, hipMemcpyAsync(d_fields, lam + (int64_t)k * n, n * 8, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, launch_copy_lam(c->storage, c->desc, k, 1, d_fields, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    c->steps = 0;
+    return LBM_OK;
+}
+
+int lbm_get_info(const lbm_ctx *c, lbm_info *info)
+{
+    if (!c || !info) return fail(nullptr, LBM_E_INVAL, "ctx or info is NULL");
+    info->tau = c->tau;
+    for (int a = 0; a < 3; ++a) info->u_ref[a] = c->u_ref[a];
+    info->shear_response = c->shear_response;
+    info->delta = c->desc.delta;
+    info->cells = c->desc.n;
+    info->fluid_cells = c->fluid_cells;
+    info->steps_done = c->steps;
+    info->arena_bytes_used = c->layout.total;
+    return LBM_OK;
+}
+
+int lbm_destroy(lbm_ctx *c)
+{
+    if (!c) return fail(nullptr, LBM_E_INVAL, "ctx is NULL");
+    const hipError_t e = hipStreamSynchronize(c->stream);
+    delete c;
+    if (e != hipSuccess) return fail(nullptr, LBM_E_DEVICE, hipGetErrorString(e));
+    return LBM_OK;
+}
+
+const char *lbm_last_error(const lbm_ctx *c) { return c ? c->err.c_str() : g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,673 @@
+// HIP kernels of the D3Q39 13-moment DDF lattice Boltzmann step for gfx950.
+//
+// The hot kernel, step_kernel, is the fused pull-stream-and-collide step of
+// Sec. 3 of the paper for f and g: each lane gathers the 78 populations of
+// one cell from shells up to three cells away, takes the moments, solves the
+// 13 Lagrange multipliers by warm-started Newton (Sec. 5 table), evaluates
+// the Knudsen sensor (Eq. eq:DeltaAvg) and alpha (Eq. eq:alpha), and writes
+// the BGK-relaxed populations to the other ping-pong buffer.
+//
+// Memory layout (structure of arrays, x fastest): a population buffer is
+// [f_0..f_38, g_0..g_38][n]; the multipliers are [13][n].  A wave owns 64
+// consecutive cells of one x-row, so every population load and store of a
+// wave is one contiguous 64-element run (unaligned by at most three elements
+// for the shifted sources).  Work is handed out in blocks of four row
+// segments; block b of a launch is mapped onto a contiguous range of segments
+// per XCD so that neighbouring rows, which share cache lines at the run ends,
+// meet in the same L2.
+#include <hip/hip_runtime.h>
+
+#include "equilibrium.h"
+#include "slot.h"
+
+namespace lbm13 {
+
+template <class S>
+struct StoreTraits;
+template <>
+struct StoreTraits<double> {
+    using C = double;
+    static constexpr bool kShift = false;
+};
+template <>
+struct StoreTraits<float> {
+    using C = float;
+    static constexpr bool kShift = true;
+};
+template <>
+struct StoreTraits<_Float16> {
+    using C = float;
+    static constexpr bool kShift = true;
+};
+
+// Coordinate of the pull source along one axis, for a cell at coordinate v
+// and velocity component c: periodic axes wrap; Neumann faces read the
+// nearest interior layer (index 3 or n - 4); on equilibrium faces the source
+// is the frozen layer itself.
+__device__ __forceinline__ int source_coord(int v, int c, int n, int periodic, int nlo, int nhi)
+{
+    int s = v - c;
+    if (periodic) {
+        s = s < 0 ? s + n : s;
+        s = s < 0 ? s + n : s;
+        s = s < 0 ? s + n : s;
+        s = s >= n ? s - n : s;
+        s = s >= n ? s - n : s;
+        s = s >= n ? s - n : s;
+    } else {
+        s = (nlo && s < 3) ? 3 : s;
+        s = (nhi && s >= n - 3) ? n - 4 : s;
+    }
+    return s;
+}
+
+__device__ __forceinline__ bool is_fluid_coord(const SlotDesc &d, int x, int y, int z)
+{
+    const int c[3] = {x, y, z};
+    const int n[3] = {d.nx, d.ny, d.nz};
+    bool f = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        f = f && !(d.open_lo[a] && c[a] < 3);
+        f = f && !(d.open_hi[a] && c[a] >= n[a] - 3);
+    }
+    return f;
+}
+
+template <class S, class C>
+__device__ __forceinline__ C load_pop(const S *buf, int64_t n, int pop, int64_t idx)
+{
+    return static_cast<C>(buf[(int64_t)pop * n + idx]);
+}
+
+// wave-level integer reductions (64 lanes)
+__device__ __forceinline__ int64_t wave_sum(int64_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ int64_t wave_max(int64_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+template <int I, class S, class C>
+__device__ __forceinline__ void gather_one(const SlotDesc &d, const S *src, int64_t cell, uint64_t links,
+                                           const int64_t (&X)[7], const int64_t (&Y)[7], const int64_t (&Z)[7],
+                                           C *hf, C *hg)
+{
+    constexpr int cx = vel(I, 0), cy = vel(I, 1), cz = vel(I, 2);
+    int64_t idx = X[cx + 3] + Y[cy + 3] + Z[cz + 3];
+    int pop = I;
+    if constexpr (I != 0) {
+        if ((links >> I) & 1ull) {  // half-way bounce-back: own opposite population
+            idx = cell;
+            pop = opposite(I);
+        }
+    }
+    C vf = load_pop<S, C>(src, d.n, pop, idx);
+    C vg = load_pop<S, C>(src, d.n, kQ + pop, idx);
+    if constexpr (StoreTraits<S>::kShift) {
+        vf *= C(d.shift_scale[I]);
+        vg *= C(d.shift_scale[kQ + I]);
+    }
+    hf[I] = vf;
+    hg[I] = vg;
+}
+
+template <class S, class C, int... I>
+__device__ __forceinline__ void gather_all(const SlotDesc &d, const S *src, int64_t cell, uint64_t links,
+                                           const int64_t (&X)[7], const int64_t (&Y)[7], const int64_t (&Z)[7],
+                                           C *hf, C *hg, std::integer_sequence<int, I...>)
+{
+    (gather_one<I>(d, src, cell, links, X, Y, Z, hf, hg), ...);
+}
+
+// eps contribution and BGK update of velocity I; stores the result
+template <int I, class S, class C>
+__device__ __forceinline__ void relax_one(const SlotDesc &d, S *dst, int64_t cell, C rho, C dT, C omega,
+                                          C f0, const C *fp, const C *fm, const C *hf, const C *hg)
+{
+    const C feq = rho * feq_of<I>(f0, fp, fm);
+    const C geq = dT * feq;
+    C of, og;
+    if constexpr (StoreTraits<S>::kShift) {
+        // deviations from the shift weights: D* = D + omega ((h_eq - w) - D)
+        const C df = hf[I], dg = hg[I];
+        of = df + omega * ((feq - C(d.shift_w[I])) - df);
+        og = dg + omega * ((geq - C(d.shift_w[kQ + I])) - dg);
+        of *= C(d.shift_inv_scale[I]);
+        og *= C(d.shift_inv_scale[kQ + I]);
+    } else {
+        of = hf[I] + omega * (feq - hf[I]);
+        og = hg[I] + omega * (geq - hg[I]);
+    }
+    dst[(int64_t)I * d.n + cell] = static_cast<S>(of);
+    dst[(int64_t)(kQ + I) * d.n + cell] = static_cast<S>(og);
+}
+
+template <class S, class C, int... I>
+__device__ __forceinline__ void relax_all(const SlotDesc &d, S *dst, int64_t cell, C rho, C dT, C omega, C f0,
+                                          const C *fp, const C *fm, const C *hf, const C *hg,
+                                          std::integer_sequence<int, I...>)
+{
+    (relax_one<I, S, C>(d, dst, cell, rho, dT, omega, f0, fp, fm, hf, hg), ...);
+}
+
+template <int I, class S, class C>
+__device__ __forceinline__ C eps_term(const SlotDesc &d, C rho, C f0, const C *fp, const C *fm, const C *hf)
+{
+    const C feq = rho * feq_of<I>(f0, fp, fm);
+    C diff;
+    if constexpr (StoreTraits<S>::kShift) diff = (C(d.shift_w[I]) - feq) + hf[I];
+    else diff = hf[I] - feq;
+    return fabs(diff) / feq;
+}
+
+template <class S, class C, int... I>
+__device__ __forceinline__ C eps_sum(const SlotDesc &d, C rho, C f0, const C *fp, const C *fm, const C *hf,
+                                     std::integer_sequence<int, I...>)
+{
+    C e = C(-0.0);
+    ((e += eps_term<I, S, C>(d, rho, f0, fp, fm, hf)), ...);
+    return e;
+}
+
+using VelSeq = std::make_integer_sequence<int, kQ>;
+
+// One fluid cell: gather, moments, Newton, sensor, BGK, store.
+template <class S>
+__device__ __forceinline__ void update_cell(const SlotDesc &d, const S *src, S *dst, int x, int y, int z,
+                                            int64_t cell, int64_t (&acc)[kStatWords])
+{
+    using C = typename StoreTraits<S>::C;
+    const uint64_t links = d.has_links ? d.links[cell] : 0ull;
+    if (links >> 63) return;  // solid
+
+    int64_t X[7], Y[7], Z[7];
+#pragma unroll
+    for (int c = -3; c <= 3; ++c) {
+        X[c + 3] = source_coord(x, c, d.nx, d.axis[0] == kAxisPeriodic, d.neumann_lo[0], d.neumann_hi[0]);
+        Y[c + 3] = (int64_t)source_coord(y, c, d.ny, d.axis[1] == kAxisPeriodic, d.neumann_lo[1], d.neumann_hi[1]) *
+                   d.nx;
+        Z[c + 3] = (int64_t)source_coord(z, c, d.nz, d.axis[2] == kAxisPeriodic, d.neumann_lo[2], d.neumann_hi[2]) *
+                   ((int64_t)d.nx * d.ny);
+    }
+
+    C hf[kQ], hg[kQ];
+    gather_all<S, C>(d, src, cell, links, X, Y, Z, hf, hg, VelSeq{});
+
+    // moments (Sec. 3; total energy 2 rho E = sum f |xi|^2 + sum g)
+    C rho, j[3], e;
+    if constexpr (StoreTraits<S>::kShift) {
+        rho = C(d.ref_mass);
+        j[0] = C(d.ref_mom[0]);
+        j[1] = C(d.ref_mom[1]);
+        j[2] = C(d.ref_mom[2]);
+        e = C(d.ref_energy);
+    } else {
+        rho = C(-0.0);
+        j[0] = j[1] = j[2] = C(-0.0);
+        e = C(-0.0);
+    }
+    {
+        C sg = hg[0];
+        rho += hf[0];
+#pragma unroll
+        for (int p = 0; p < kPairs; ++p) {
+            const C sp = hf[2 * p + 1] + hf[2 * p + 2];
+            const C ap = hf[2 * p + 1] - hf[2 * p + 2];
+            rho += sp;
+            j[0] += C(kPairVel[p][0]) * ap;
+            j[1] += C(kPairVel[p][1]) * ap;
+            j[2] += C(kPairVel[p][2]) * ap;
+            e += C(pair_q(p)) * sp;
+            sg += hg[2 * p + 1] + hg[2 * p + 2];
+        }
+        e += sg;
+    }
+    C u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+    const C uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const C T = (e - rho * uu) / (C(d.two_cv) * rho);
+
+    C m[kM];
+    mb_targets(u, T, m);
+
+    C lam[kM];
+    C *lam_buf = static_cast<C *>(d.lam);
+#pragma unroll
+    for (int k = 0; k < kM; ++k) lam[k] = lam_buf[(int64_t)k * d.n + cell];
+
+    C f0, fp[kPairs], fm[kPairs];
+    int iters = 0;
+    const int status = solve_multipliers<C>(m, u, T, lam, f0, fp, fm, C(d.tol), d.maxit, d.maxit_cold, iters);
+
+    // Knudsen sensor over f (Eq. eq:DeltaAvg) and relaxation branch (Eq. eq:alpha)
+    const C eps = eps_sum<S, C>(d, rho, f0, fp, fm, hf, VelSeq{}) / C(kQ);
+    int br = 0;
+    if (d.kn_relax) br = (eps < C(1e-2)) ? 0 : (eps < C(1e-1)) ? 1 : (eps < C(1)) ? 2 : 3;
+    const C omega = C(br == 0 ? d.omega[0] : br == 1 ? d.omega[1] : br == 2 ? d.omega[2] : d.omega[3]);
+    const C dT = C(d.delta) * T;
+
+    relax_all<S, C>(d, dst, cell, rho, dT, omega, f0, fp, fm, hf, hg, VelSeq{});
+#pragma unroll
+    for (int k = 0; k < kM; ++k) lam_buf[(int64_t)k * d.n + cell] = lam[k];
+
+    acc[0] += iters;
+    acc[1] = iters > acc[1] ? iters : acc[1];
+    acc[2] += status == kFailed;
+    acc[3] += status == kConvergedCold;
+    acc[4] += br == 0;
+    acc[5] += br == 1;
+    acc[6] += br == 2;
+    acc[7] += br == 3;
+}
+
+// Locate the slot that owns logical block b (uniform across the block).
+__device__ __forceinline__ int find_slot(const SlotTable *tab, int b)
+{
+    int s = 0;
+    while (s + 1 < tab->nslots && tab->block_start[s + 1] <= b) ++s;
+    return s;
+}
+
+// Batched fused step.  Launch j of a sequence advances every slot with
+// j < steps_todo from buffer (parity0 + j) & 1 to the other one.  The grid
+// (a multiple of 8 blocks) is persistent: blocks stride over the logical
+// blocks of all slots, each XCD over its own contiguous range.
+template <class S>
+__global__ __launch_bounds__(kBlockThreads) void step_kernel(const SlotTable *__restrict__ tab, int j,
+                                                             int64_t *__restrict__ stats)
+{
+    int64_t acc[kStatWords] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int total = tab->total_blocks;
+    const int xcd = blockIdx.x & 7;
+    const int per_xcd = gridDim.x >> 3;
+    const int lo = (int)(((int64_t)total * xcd) >> 3);
+    const int hi = (int)(((int64_t)total * (xcd + 1)) >> 3);
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    for (int b = lo + (int)(blockIdx.x >> 3); b < hi; b += per_xcd) {
+        const int s = find_slot(tab, b);
+        const SlotDesc &d = tab->slot[s];
+        if (j >= d.steps_todo) continue;
+        const int64_t seg = (int64_t)(b - tab->block_start[s]) * kWavesPerBlock + wave;
+        if (seg >= d.segments) continue;
+        const int segx = (int)(seg % d.nsegx);
+        const int64_t row = seg / d.nsegx;
+        const int y = (int)(row % d.ny);
+        const int z = (int)(row / d.ny);
+        const int x = segx * kSegment + lane;
+        if (x >= d.nx) continue;
+        if (!is_fluid_coord(d, x, y, z)) continue;
+        const int par = (d.parity0 + j) & 1;
+        const S *src = static_cast<const S *>(d.buf[par]);
+        S *dst = static_cast<S *>(d.buf[par ^ 1]);
+        const int64_t cell = (int64_t)x + (int64_t)d.nx * ((int64_t)y + (int64_t)d.ny * z);
+        update_cell<S>(d, src, dst, x, y, z, cell, acc);
+    }
+    if (stats) {
+        int64_t red[kStatWords];
+#pragma unroll
+        for (int k = 0; k < kStatWords; ++k) red[k] = (k == 1) ? wave_max(acc[k]) : wave_sum(acc[k]);
+        if (lane == 0) {
+            int64_t *p = stats + ((int64_t)blockIdx.x * kWavesPerBlock + wave) * kStatWords;
+#pragma unroll
+            for (int k = 0; k < kStatWords; ++k) p[k] = (k == 1) ? (red[k] > p[k] ? red[k] : p[k]) : p[k] + red[k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Initial state: the equilibrium of the given fields, cold-started in FP64.
+// fields: rho[n], ux[n], uy[n], uz[n], T[n] (FP64).  Writes both buffers and
+// the multipliers.  failed (int64) counts cells whose Newton did not converge.
+template <class S>
+__global__ __launch_bounds__(256) void init_kernel(SlotDesc d, const double *__restrict__ fields,
+                                                   unsigned long long *failed)
+{
+    using C = typename StoreTraits<S>::C;
+    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= d.n) return;
+    const double rho = fields[cell];
+    const double u[3] = {fields[d.n + cell], fields[2 * d.n + cell], fields[3 * d.n + cell]};
+    const double T = fields[4 * d.n + cell];
+    double m[kM], lam[kM], f0, fp[kPairs], fm[kPairs];
+    mb_targets(u, T, m);
+    cold_guess(u, T, lam);
+    int iters = 0;
+    const int maxit = d.maxit_cold;
+    const int st = solve_multipliers<double>(m, u, T, lam, f0, fp, fm, d.tol, maxit, maxit, iters);
+    if (st == kFailed) atomicAdd(failed, 1ull);
+    const double dT = d.delta * T;
+    S *b0 = static_cast<S *>(d.buf[0]);
+    S *b1 = static_cast<S *>(d.buf[1]);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const double e = (i == 0) ? f0 : (((i - 1) & 1) == 0 ? fp[(i - 1) >> 1] : fm[(i - 1) >> 1]);
+        const double feq = rho * e;
+        const double geq = dT * feq;
+        double vf = feq, vg = geq;
+        if constexpr (StoreTraits<S>::kShift) {
+            vf = (feq - (double)d.shift_w[i]) * (double)d.shift_inv_scale[i];
+            vg = (geq - (double)d.shift_w[kQ + i]) * (double)d.shift_inv_scale[kQ + i];
+        }
+        const S sf = static_cast<S>(vf), sg = static_cast<S>(vg);
+        b0[(int64_t)i * d.n + cell] = sf;
+        b1[(int64_t)i * d.n + cell] = sf;
+        b0[(int64_t)(kQ + i) * d.n + cell] = sg;
+        b1[(int64_t)(kQ + i) * d.n + cell] = sg;
+    }
+    C *lb = static_cast<C *>(d.lam);
+#pragma unroll
+    for (int k = 0; k < kM; ++k) lb[(int64_t)k * d.n + cell] = static_cast<C>(lam[k]);
+}
+
+// Equilibrium of one state (used by the host for shift weights and the shear
+// response).  out: feq[39] per unit density followed by lam[13].
+__global__ void single_equilibrium_kernel(double rho, double ux, double uy, double uz, double T, double tol,
+                                          int maxit, double *out, int *status)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const double u[3] = {ux, uy, uz};
+    double m[kM], lam[kM], f0, fp[kPairs], fm[kPairs];
+    mb_targets(u, T, m);
+    cold_guess(u, T, lam);
+    int iters = 0;
+    *status = solve_multipliers<double>(m, u, T, lam, f0, fp, fm, tol, maxit, maxit, iters);
+    for (int i = 0; i < kQ; ++i)
+        out[i] = rho * ((i == 0) ? f0 : (((i - 1) & 1) == 0 ? fp[(i - 1) >> 1] : fm[(i - 1) >> 1]));
+    for (int k = 0; k < kM; ++k) out[kQ + k] = lam[k];
+    (void)rho;
+}
+
+// ---------------------------------------------------------------------------
+// Moments of the stored state in FP64 (rho, ux, uy, uz, T per cell) and
+// per-block partial totals over fluid cells (mass, momentum, energy).
+template <class S>
+__global__ __launch_bounds__(256) void moments_kernel(SlotDesc d, int parity, double *__restrict__ out,
+                                                      double *__restrict__ partial)
+{
+    __shared__ double red[5][256];
+    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double t[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (cell < d.n) {
+        const int x = (int)(cell % d.nx);
+        const int y = (int)((cell / d.nx) % d.ny);
+        const int z = (int)(cell / ((int64_t)d.nx * d.ny));
+        const bool solid = d.has_links && (d.links[cell] >> 63);
+        if (solid) {
+            for (int k = 0; k < 5; ++k) out[(int64_t)k * d.n + cell] = __builtin_nan("");
+        } else {
+            // Neumann boundary cells report the interior cell they copy;
+            // equilibrium-face cells (which take precedence) report themselves
+            int c[3] = {x, y, z};
+            const int n[3] = {d.nx, d.ny, d.nz};
+            bool in_eq = false;
+            for (int a = 0; a < 3; ++a) {
+                in_eq = in_eq || (d.open_lo[a] && !d.neumann_lo[a] && c[a] < 3);
+                in_eq = in_eq || (d.open_hi[a] && !d.neumann_hi[a] && c[a] >= n[a] - 3);
+                if (d.neumann_lo[a] && c[a] < 3) c[a] = 3;
+                if (d.neumann_hi[a] && c[a] >= n[a] - 3) c[a] = n[a] - 4;
+            }
+            const int64_t src =
+                in_eq ? cell : (int64_t)c[0] + (int64_t)d.nx * ((int64_t)c[1] + (int64_t)d.ny * c[2]);
+            const S *b = static_cast<const S *>(d.buf[parity]);
+            double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0, e = 0.0;
+            for (int i = 0; i < kQ; ++i) {
+                double vf = (double)b[(int64_t)i * d.n + src];
+                double vg = (double)b[(int64_t)(kQ + i) * d.n + src];
+                if constexpr (StoreTraits<S>::kShift) {
+                    vf = (double)d.shift_w[i] + vf * (double)d.shift_scale[i];
+                    vg = (double)d.shift_w[kQ + i] + vg * (double)d.shift_scale[kQ + i];
+                }
+                const int cx = vel(i, 0), cy = vel(i, 1), cz = vel(i, 2);
+                r += vf;
+                jx += vf * cx;
+                jy += vf * cy;
+                jz += vf * cz;
+                e += vf * (double)(cx * cx + cy * cy + cz * cz) + vg;
+            }
+            const double ux = jx / r, uy = jy / r, uz = jz / r;
+            const double T = (e - r * (ux * ux + uy * uy + uz * uz)) / (d.two_cv * r);
+            out[cell] = r;
+            out[d.n + cell] = ux;
+            out[2 * d.n + cell] = uy;
+            out[3 * d.n + cell] = uz;
+            out[4 * d.n + cell] = T;
+            if (is_fluid_coord(d, x, y, z)) {
+                t[0] = r;
+                t[1] = jx;
+                t[2] = jy;
+                t[3] = jz;
+                t[4] = 0.5 * e;
+            }
+        }
+    }
+    for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = t[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 5; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 5; ++k) partial[(int64_t)blockIdx.x * 5 + k] = red[k][0];
+}
+
+// Fixed-order sum of the per-block partials (one block).  Also flags
+// non-finite fluid moments through the totals.
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const double *__restrict__ partial, int nblocks,
+                                                              double *__restrict__ totals)
+{
+    __shared__ double red[5][256];
+    double t[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+        for (int k = 0; k < 5; ++k) t[k] += partial[(int64_t)b * 5 + k];
+    for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = t[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 5; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 5; ++k) totals[k] = red[k][0];
+}
+
+// Per-wave statistics partials -> totals (one block).
+__global__ __launch_bounds__(256) void reduce_stats_kernel(const int64_t *__restrict__ partial, int nwaves,
+                                                           int64_t *__restrict__ out)
+{
+    __shared__ int64_t red[kStatWords][256];
+    int64_t t[kStatWords] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int w = threadIdx.x; w < nwaves; w += blockDim.x)
+        for (int k = 0; k < kStatWords; ++k) {
+            const int64_t v = partial[(int64_t)w * kStatWords + k];
+            t[k] = (k == 1) ? (v > t[k] ? v : t[k]) : t[k] + v;
+        }
+    for (int k = 0; k < kStatWords; ++k) red[k][threadIdx.x] = t[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < kStatWords; ++k) {
+                const int64_t a = red[k][threadIdx.x], b = red[k][threadIdx.x + s];
+                red[k][threadIdx.x] = (k == 1) ? (a > b ? a : b) : a + b;
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < kStatWords; ++k) out[k] = red[k][0];
+}
+
+// Fill with zero (a kernel rather than a memset node, so that the sequence
+// can be captured into a graph).
+__global__ void zero_kernel(int64_t *p, int64_t count)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// Decode population `pop` of buffer `parity` to FP64 (get_state), or encode
+// FP64 into both buffers (set_state).
+template <class S>
+__global__ void decode_pop_kernel(SlotDesc d, int parity, int pop, double *__restrict__ out)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.n) return;
+    const S *b = static_cast<const S *>(d.buf[parity]);
+    double v = (double)b[(int64_t)pop * d.n + c];
+    if constexpr (StoreTraits<S>::kShift) v = (double)d.shift_w[pop] + v * (double)d.shift_scale[pop];
+    out[c] = v;
+}
+
+template <class S>
+__global__ void encode_pop_kernel(SlotDesc d, int pop, const double *__restrict__ in)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.n) return;
+    double v = in[c];
+    if constexpr (StoreTraits<S>::kShift) v = (v - (double)d.shift_w[pop]) * (double)d.shift_inv_scale[pop];
+    const S s = static_cast<S>(v);
+    static_cast<S *>(d.buf[0])[(int64_t)pop * d.n + c] = s;
+    static_cast<S *>(d.buf[1])[(int64_t)pop * d.n + c] = s;
+}
+
+template <class C>
+__global__ void copy_lam_kernel(SlotDesc d, int k, int to_device, double *__restrict__ host_side)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.n) return;
+    C *l = static_cast<C *>(d.lam) + (int64_t)k * d.n;
+    if (to_device) l[i] = static_cast<C>(host_side[i]);
+    else host_side[i] = (double)l[i];
+}
+
+}  // namespace lbm13
+
+// ---------------------------------------------------------------------------
+// Launch wrappers used by the C ABI layer (C++ linkage, internal).
+#include "launch.h"
+
+namespace lbm13 {
+
+template <class S>
+static hipError_t launch_step_t(const SlotTable *tab, int grid, int j, int64_t *stats, hipStream_t st)
+{
+    hipLaunchKernelGGL(step_kernel<S>, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_step(int storage, const SlotTable *tab, int grid, int j, int64_t *stats, hipStream_t st)
+{
+    switch (storage) {
+    case kStoreF64: return launch_step_t<double>(tab, grid, j, stats, st);
+    case kStoreF32: return launch_step_t<float>(tab, grid, j, stats, st);
+    default: return launch_step_t<_Float16>(tab, grid, j, stats, st);
+    }
+}
+
+const void *step_kernel_symbol(int storage)
+{
+    switch (storage) {
+    case kStoreF64: return reinterpret_cast<const void *>(&step_kernel<double>);
+    case kStoreF32: return reinterpret_cast<const void *>(&step_kernel<float>);
+    default: return reinterpret_cast<const void *>(&step_kernel<_Float16>);
+    }
+}
+
+hipError_t launch_init(int storage, const SlotDesc &d, const double *fields, unsigned long long *failed,
+                       hipStream_t st)
+{
+    const int grid = (int)((d.n + 255) / 256);
+    switch (storage) {
+    case kStoreF64: hipLaunchKernelGGL(init_kernel<double>, dim3(grid), dim3(256), 0, st, d, fields, failed); break;
+    case kStoreF32: hipLaunchKernelGGL(init_kernel<float>, dim3(grid), dim3(256), 0, st, d, fields, failed); break;
+    default: hipLaunchKernelGGL(init_kernel<_Float16>, dim3(grid), dim3(256), 0, st, d, fields, failed); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_single_equilibrium(double rho, const double u[3], double T, double tol, int maxit, double *out,
+                                     int *status, hipStream_t st)
+{
+    hipLaunchKernelGGL(single_equilibrium_kernel, dim3(1), dim3(64), 0, st, rho, u[0], u[1], u[2], T, tol, maxit,
+                       out, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(int storage, const SlotDesc &d, int parity, double *out, double *partial, double *totals,
+                          hipStream_t st)
+{
+    const int grid = (int)((d.n + 255) / 256);
+    switch (storage) {
+    case kStoreF64:
+        hipLaunchKernelGGL(moments_kernel<double>, dim3(grid), dim3(256), 0, st, d, parity, out, partial);
+        break;
+    case kStoreF32:
+        hipLaunchKernelGGL(moments_kernel<float>, dim3(grid), dim3(256), 0, st, d, parity, out, partial);
+        break;
+    default:
+        hipLaunchKernelGGL(moments_kernel<_Float16>, dim3(grid), dim3(256), 0, st, d, parity, out, partial);
+        break;
+    }
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, st, partial, grid, totals);
+    return hipGetLastError();
+}
+
+int moments_partial_blocks(int64_t n) { return (int)((n + 255) / 256); }
+
+hipError_t launch_zero(int64_t *p, int64_t count, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    int grid = (int)((count + 255) / 256);
+    grid = grid > 1024 ? 1024 : grid;
+    hipLaunchKernelGGL(zero_kernel, dim3(grid), dim3(256), 0, st, p, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_stats(const int64_t *partial, int nwaves, int64_t *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(reduce_stats_kernel, dim3(1), dim3(256), 0, st, partial, nwaves, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_decode_pop(int storage, const SlotDesc &d, int parity, int pop, double *out, hipStream_t st)
+{
+    const int grid = (int)((d.n + 255) / 256);
+    switch (storage) {
+    case kStoreF64: hipLaunchKernelGGL(decode_pop_kernel<double>, dim3(grid), dim3(256), 0, st, d, parity, pop, out); break;
+    case kStoreF32: hipLaunchKernelGGL(decode_pop_kernel<float>, dim3(grid), dim3(256), 0, st, d, parity, pop, out); break;
+    default: hipLaunchKernelGGL(decode_pop_kernel<_Float16>, dim3(grid), dim3(256), 0, st, d, parity, pop, out); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_encode_pop(int storage, const SlotDesc &d, int pop, const double *in, hipStream_t st)
+{
+    const int grid = (int)((d.n + 255) / 256);
+    switch (storage) {
+    case kStoreF64: hipLaunchKernelGGL(encode_pop_kernel<double>, dim3(grid), dim3(256), 0, st, d, pop, in); break;
+    case kStoreF32: hipLaunchKernelGGL(encode_pop_kernel<float>, dim3(grid), dim3(256), 0, st, d, pop, in); break;
+    default: hipLaunchKernelGGL(encode_pop_kernel<_Float16>, dim3(grid), dim3(256), 0, st, d, pop, in); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_lam(int storage, const SlotDesc &d, int k, int to_device, double *host_side, hipStream_t st)
+{
+    const int grid = (int)((d.n + 255) / 256);
+    if (storage == kStoreF64)
+        hipLaunchKernelGGL(copy_lam_kernel<double>, dim3(grid), dim3(256), 0, st, d, k, to_device, host_side);
+    else
+        hipLaunchKernelGGL(copy_lam_kernel<float>, dim3(grid), dim3(256), 0, st, d, k, to_device, host_side);
+    return hipGetLastError();
+}
+
+}  // namespace lbm13

@@ -1,0 +1,83 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol
+declared in include/lbm.h, validates parameters and reports the interface
+conventions (velocity order) that the oracle shares."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1910_13515_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(lbm.LIB_PATH):
+        from paper_1910_13515_amd import build
+        build.build()
+    return lbm.load()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared_functions()
+    assert "lbm_create" in names and "lbm_step" in names and "lbm_moments" in names and "lbm_destroy" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(lbm.EXPORTED) <= set(names)
+
+
+def test_version_and_velocity_order_match_oracle(L, orc):
+    assert lbm.lbm_version() >= 10000
+    np.testing.assert_array_equal(lbm.lbm_velocities(), orc.velocities())
+
+
+def test_parameter_validation_without_device(L):
+    good = lbm.make_params((16, 8, 1), tau=0.6)
+    assert lbm.lbm_required_bytes(good) > 0
+    bad = [
+        lbm.make_params((0, 8, 1), tau=0.6),
+        lbm.make_params((16, 8, 1), tau=0.4),
+        lbm.make_params((16, 8, 1), tau=0.6, gamma=1.8),
+        lbm.make_params((16, 8, 1), tau=0.6, faces=(1, 0, 0, 0, 0, 0)),   # mixed periodic axis
+        lbm.make_params((6, 8, 1), tau=0.6, faces=(1, 1, 0, 0, 0, 0)),    # too short for open faces
+        lbm.make_params((16, 8, 1), tau=0.0),                              # no tau and no Reynolds
+        lbm.make_params((16, 8, 1), tau=0.6, storage=7),
+        lbm.make_params((16, 8, 1), tau=0.6, mach=0.5, u_dir=(0, 0, 0)),
+    ]
+    for p in bad:
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_required_bytes(p)
+        assert e.value.code == lbm.LBM_E_INVAL
+    assert lbm.load().lbm_required_bytes(None) == lbm.LBM_E_INVAL
+    assert b"NULL" in lbm.load().lbm_last_error(None)
+
+
+def test_required_bytes_scale_with_storage(L):
+    n = 64 * 32 * 16
+    b64 = lbm.lbm_required_bytes(lbm.make_params((64, 32, 16), tau=0.6, storage="fp64"))
+    b32 = lbm.lbm_required_bytes(lbm.make_params((64, 32, 16), tau=0.6, storage="fp32s"))
+    b16 = lbm.lbm_required_bytes(lbm.make_params((64, 32, 16), tau=0.6, storage="fp16s"))
+    # two ping-pong buffers of 78 populations plus the multipliers dominate
+    assert b64 >= n * (2 * 78 * 8 + 13 * 8)
+    assert b32 >= n * (2 * 78 * 4 + 13 * 4)
+    assert b16 >= n * (2 * 78 * 2 + 13 * 4)
+    assert b64 > b32 > b16
+
+
+def test_null_arguments_are_rejected(L):
+    p = lbm.make_params((16, 8, 1), tau=0.6)
+    ctx = ctypes.c_void_p()
+    assert L.lbm_create(ctypes.byref(p), None, 1 << 20, None, ctypes.byref(ctx)) == lbm.LBM_E_INVAL
+    assert L.lbm_create(ctypes.byref(p), ctypes.c_void_p(256), 16, None, ctypes.byref(ctx)) == lbm.LBM_E_NOMEM
+    assert L.lbm_step(None, 1, None) == lbm.LBM_E_INVAL
+    assert L.lbm_moments(None, None, None) == lbm.LBM_E_INVAL
+    assert L.lbm_destroy(None) == lbm.LBM_E_INVAL
