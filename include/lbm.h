@@ -99,6 +99,8 @@ typedef struct {
     int64_t failed;            /* cell-steps whose Newton did not converge */
     int64_t cold_restarts;     /* cell-steps whose warm start failed and were restarted cold */
     int64_t alpha_hist[4];     /* cell-steps per branch of Eq. (eq:alpha) */
+    int64_t wave_iterations;   /* sum over wave-steps of the largest count in the wave (64 cells) */
+    int64_t waves;             /* wave-steps (a wave runs as many Newton updates as its slowest cell) */
 } lbm_step_stats;
 
 /* Values derived by lbm_create(). */

@@ -69,6 +69,16 @@ __host__ __device__ constexpr int phi_pair(int k, int p)
     return 0;
 }
 
+// index 0..5 of the velocity shell |xi|^2 in {0, 1, 3, 4, 8, 9}
+__host__ __device__ constexpr int shell_of_q(int q)
+{
+    return q == 0 ? 0 : q == 1 ? 1 : q == 3 ? 2 : q == 4 ? 3 : q == 8 ? 4 : 5;
+}
+__host__ __device__ constexpr int shell(int i)
+{
+    return shell_of_q(vel(i, 0) * vel(i, 0) + vel(i, 1) * vel(i, 1) + vel(i, 2) * vel(i, 2));
+}
+
 __host__ __device__ constexpr bool basis_odd(int k) { return (k >= 1 && k <= 3) || k >= 10; }
 
 // acc + c * v with the constant c folded at compile time (0: nothing,
@@ -98,7 +108,7 @@ struct Term<-1> {
 template <int K, class T, int... P>
 __device__ __forceinline__ T basis_sum(const T *v, std::integer_sequence<int, P...>)
 {
-    T acc = T(0);
+    T acc = T(-0.0);  // -0 + v folds to v
     ((acc = Term<phi_pair(K, P)>::add(acc, v[P])), ...);
     return acc;
 }
@@ -107,7 +117,7 @@ __device__ __forceinline__ T basis_sum(const T *v, std::integer_sequence<int, P.
 template <int K, int L, class T, int... P>
 __device__ __forceinline__ T gram_sum(const T *v, std::integer_sequence<int, P...>)
 {
-    T acc = T(0);
+    T acc = T(-0.0);  // -0 + v folds to v
     ((acc = Term<phi_pair(K, P) * phi_pair(L, P)>::add(acc, v[P])), ...);
     return acc;
 }
@@ -116,7 +126,7 @@ __device__ __forceinline__ T gram_sum(const T *v, std::integer_sequence<int, P..
 template <bool Odd, int P, class T, int... K>
 __device__ __forceinline__ T exponent_part(const T *lam, std::integer_sequence<int, K...>)
 {
-    T acc = T(0);
+    T acc = T(-0.0);  // -0 + v folds to v
     ((acc = (basis_odd(K) == Odd) ? Term<phi_pair(K, P)>::add(acc, lam[K]) : acc), ...);
     return acc;
 }

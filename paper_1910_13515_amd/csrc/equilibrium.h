@@ -16,7 +16,7 @@ __device__ __forceinline__ C dexp(C x);
 template <>
 __device__ __forceinline__ double dexp<double>(double x) { return exp(x); }
 template <>
-__device__ __forceinline__ float dexp<float>(float x) { return expf(x); }
+__device__ __forceinline__ float dexp<float>(float x) { return __expf(x); }  // v_exp_f32 on x log2(e)
 
 template <class C>
 __device__ __forceinline__ C dlog(C x);
@@ -31,6 +31,13 @@ template <>
 __device__ __forceinline__ double dsqrt<double>(double x) { return sqrt(x); }
 template <>
 __device__ __forceinline__ float dsqrt<float>(float x) { return sqrtf(x); }
+
+// 1/sqrt(x) and 1/x: exact division in FP64; the hardware approximations
+// (about 1 ulp) in the FP32 path.
+__device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Maxwell-Boltzmann targets per unit density (Eq. eq:EqMomentsTensor, the 13
 // constraints of Eq. eq:13constraints; the contracted third moment is
@@ -78,12 +85,25 @@ __device__ __forceinline__ void eval_exponentials(const C lam[kM], C &f0, C fp[k
     eval_pairs(lam, fp, fm, PairSeq{});
 }
 
+// Target k of mb_targets evaluated from (u, T, h = |u|^2 + 5T)
+template <int K, class C>
+__device__ __forceinline__ C target(const C u[3], C T, C h)
+{
+    if constexpr (K == 0) return C(1);
+    else if constexpr (K <= 3) return u[K - 1];
+    else if constexpr (K <= 6) return u[K - 4] * u[K - 4] + T;
+    else if constexpr (K == 7) return u[0] * u[1];
+    else if constexpr (K == 8) return u[0] * u[2];
+    else if constexpr (K == 9) return u[1] * u[2];
+    else return h * u[K - 10];
+}
+
 // G_k = sum_i exp(phi_i . lam) phi_ik - m_k from pair sums s and differences a
 template <class C, int... K>
-__device__ __forceinline__ void residual_impl(C f0, const C *s, const C *a, const C *m, C *G,
+__device__ __forceinline__ void residual_impl(C f0, const C *s, const C *a, const C u[3], C T, C h, C *G,
                                               std::integer_sequence<int, K...>)
 {
-    ((G[K] = ((K == 0) ? f0 : C(-0.0)) + basis_sum<K>(basis_odd(K) ? a : s, PairSeq{}) - m[K]), ...);
+    ((G[K] = ((K == 0) ? f0 : C(-0.0)) + basis_sum<K>(basis_odd(K) ? a : s, PairSeq{}) - target<K>(u, T, h)), ...);
 }
 
 template <int K, int L, class C>
@@ -123,7 +143,7 @@ __device__ __forceinline__ bool cholesky_solve(C (&J)[kM][kM], const C G[kM], C 
 #pragma unroll
         for (int k = 0; k < j; ++k) s -= J[j][k] * J[j][k];
         ok = ok && (s > C(0));
-        const C r = C(1) / dsqrt(s);
+        const C r = rsqrt_(s);
         rdiag[j] = r;
 #pragma unroll
         for (int i = j + 1; i < kM; ++i) {
@@ -177,30 +197,30 @@ __device__ __forceinline__ void cold_guess(const C u[3], C T, C lam[kM])
 // not finite) the solve restarts once from the Maxwellian shape with cap
 // maxit_cold.  On return lam, f0, fp, fm hold the last accepted iterate and
 // iters the number of accepted updates of the final attempt (maxit if both
-// attempts failed).
+// attempts failed).  The targets m are evaluated from (u, T) where needed.
 template <class C>
-__device__ __forceinline__ int solve_multipliers(const C m[kM], const C u[3], C T, C lam[kM], C &f0, C fp[kPairs],
-                                                 C fm[kPairs], C tol, int maxit, int maxit_cold, int &iters)
+__device__ __forceinline__ int solve_multipliers(const C u[3], C T, C lam[kM], C &f0, C fp[kPairs], C fm[kPairs],
+                                                 C tol, int maxit, int maxit_cold, int &iters, C (&resid)[5])
 {
+    C m[kM];
+    mb_targets(u, T, m);
     C scale = C(1);
 #pragma unroll
     for (int k = 0; k < kM; ++k) scale = fabs(m[k]) > scale ? fabs(m[k]) : scale;
     const C bound = tol * scale;
+    const C h = u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + C(5) * T;
 
-    C base[kM], d[kM];
+    // lam holds the trial point lam_acc - t d; a rejected trial moves back by
+    // half its step (t -> t/2)
+    C d[kM];
 #pragma unroll
-    for (int k = 0; k < kM; ++k) {
-        base[k] = lam[k];
-        d[k] = C(0);
-    }
+    for (int k = 0; k < kM; ++k) d[k] = C(0);
     C t = C(0);
     C n0 = C(0);
     int it = 0, ls = 0, cap = maxit;
     bool fresh = true, cold = false;
     int status = kFailed;
     for (;;) {
-#pragma unroll
-        for (int k = 0; k < kM; ++k) lam[k] = base[k] - t * d[k];
         eval_exponentials(lam, f0, fp, fm);
         C s[kPairs], a[kPairs];
 #pragma unroll
@@ -209,7 +229,7 @@ __device__ __forceinline__ int solve_multipliers(const C m[kM], const C u[3], C 
             a[p] = fp[p] - fm[p];
         }
         C G[kM];
-        residual_impl(f0, s, a, m, G, BasisSeq{});
+        residual_impl(f0, s, a, u, T, h, G, BasisSeq{});
         C n2 = C(0);
 #pragma unroll
         for (int k = 0; k < kM; ++k) n2 += G[k] * G[k];
@@ -217,6 +237,8 @@ __device__ __forceinline__ int solve_multipliers(const C m[kM], const C u[3], C 
         if (!fresh && !(n2 < n0) && ls < 39) {
             t *= C(0.5);
             ++ls;
+#pragma unroll
+            for (int k = 0; k < kM; ++k) lam[k] += t * d[k];
             continue;
         }
         if (!fresh) ++it;
@@ -227,6 +249,13 @@ __device__ __forceinline__ int solve_multipliers(const C m[kM], const C u[3], C 
             const C g = fabs(G[k]);
             r = (g <= r) ? r : g;  // NaN propagates
         }
+        // residuals of the collision invariants at the accepted iterate:
+        // mass, momentum, and sum_i f_i |xi_i|^2 (trace of the second moment)
+        resid[0] = G[0];
+        resid[1] = G[1];
+        resid[2] = G[2];
+        resid[3] = G[3];
+        resid[4] = G[4] + G[5] + G[6];
         if (r <= bound) {
             status = cold ? kConvergedCold : kConverged;
             break;
@@ -243,24 +272,54 @@ __device__ __forceinline__ int solve_multipliers(const C m[kM], const C u[3], C 
                 break;
             }
             cold = true;
-            cold_guess(u, T, base);
-#pragma unroll
-            for (int k = 0; k < kM; ++k) d[k] = C(0);
-            t = C(0);
+            cold_guess(u, T, lam);
             it = 0;
             ls = 0;
             cap = maxit_cold;
             fresh = true;
             continue;
         }
-#pragma unroll
-        for (int k = 0; k < kM; ++k) base[k] = lam[k];
         t = C(1);
         ls = 0;
         n0 = n2;
+#pragma unroll
+        for (int k = 0; k < kM; ++k) lam[k] -= d[k];
     }
     iters = status == kFailed ? maxit : it;
     return status;
+}
+
+// Remove the residual of the collision invariants from an equilibrium (per
+// unit density) that satisfies the constraints only to a tolerance:
+// f_i += w_i (a + b . xi_i + c |xi_i|^2) with the isotropic rest weights w
+// of each shell, so that sum_i f_i (1, xi_i, |xi_i|^2) is exact.  With
+// isotropic weights the five equations decouple: b_a = -R_a / W2 and (a, c)
+// from the 2x2 system [[W0, Wq], [Wq, Wqq]] (a, c) = -(R_0, R_E), whose
+// inverse is passed in (inv = {i00, i01, i11}).
+template <int P, class C>
+__device__ __forceinline__ void project_pair(C *fp, C *fm, C a, C c, const C b[3], const float *wshell)
+{
+    constexpr int cx = kPairVel[P][0], cy = kPairVel[P][1], cz = kPairVel[P][2];
+    const C w = C(wshell[shell_of_q(pair_q(P))]);
+    const C even = w * (a + C(pair_q(P)) * c);
+    C odd = C(-0.0);
+    odd = Term<cx>::add(odd, b[0]);
+    odd = Term<cy>::add(odd, b[1]);
+    odd = Term<cz>::add(odd, b[2]);
+    odd *= w;
+    fp[P] += even + odd;
+    fm[P] += even - odd;
+}
+
+template <class C, int... P>
+__device__ __forceinline__ void project_invariants(C &f0, C *fp, C *fm, const C (&resid)[5], const float *wshell,
+                                                   const float *inv, float inv_w2, std::integer_sequence<int, P...>)
+{
+    const C a = -(C(inv[0]) * resid[0] + C(inv[1]) * resid[4]);
+    const C c = -(C(inv[1]) * resid[0] + C(inv[2]) * resid[4]);
+    const C b[3] = {-resid[1] * C(inv_w2), -resid[2] * C(inv_w2), -resid[3] * C(inv_w2)};
+    f0 += C(wshell[0]) * a;
+    (project_pair<P, C>(fp, fm, a, c, b, wshell), ...);
 }
 
 // equilibrium per unit density of velocity i from the solve's exponentials

@@ -72,8 +72,9 @@ std::string validate(const lbm_params *p)
     if (!p) return "params is NULL";
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return "grid dimensions must be >= 1";
     const int64_t n = (int64_t)p->nx * p->ny * p->nz;
-    if (n > (int64_t)1 << 40) return "grid too large";
     if (p->storage < LBM_STORE_FP64 || p->storage > LBM_STORE_FP16_SHIFTED) return "unknown storage mode";
+    // the kernels address two population arrays from one base with 32-bit byte offsets
+    if (2 * n * storage_bytes(p->storage) >= ((int64_t)1 << 32)) return "grid too large for this storage mode";
     if (p->shift_ref < 0 || p->shift_ref > 1) return "shift_ref must be 0 or 1";
     const int dims[3] = {p->nx, p->ny, p->nz};
     for (int a = 0; a < 3; ++a) {
@@ -367,11 +368,23 @@ int lbm_create(const lbm_params *params, void *dev_arena, int64_t arena_bytes, v
             w[kQ + i] = delta * p.T_ref * w[i];
         }
         double mass = 0, mom[3] = {0, 0, 0}, ener = 0;
-        for (int i = 0; i < 2 * kQ; ++i) {
-            d.shift_w[i] = (float)w[i];
-            const double sc = p.storage == LBM_STORE_FP16_SHIFTED ? pow2_near(w[i] > 0 ? w[i] : w[i % kQ]) : 1.0;
-            d.shift_scale[i] = (float)sc;
-            d.shift_inv_scale[i] = (float)(1.0 / sc);
+        // shift weights on a 2^-21 grid: every weight and every sum of the
+        // weights below (all < 8 in magnitude) is then exact in FP32, so the
+        // FP32 moments carry no constant rounding bias from the shift
+        for (int i = 0; i < 2 * kQ; ++i) d.shift_w[i] = (float)(std::nearbyint(std::ldexp(w[i], 21)) * std::ldexp(1.0, -21));
+        // FP16: one power-of-two scale per velocity shell, from the rest-state
+        // weight of the shell (g: times delta T_ref when delta > 0); FP32: 1
+        for (int sh = 0; sh < 6; ++sh) {
+            double sf = 1.0, sg = 1.0;
+            if (p.storage == LBM_STORE_FP16_SHIFTED) {
+                for (int i = 0; i < kQ; ++i)
+                    if (shell(i) == sh) sf = pow2_near(p.rho_ref * rest[i]);
+                sg = delta > 0.0 ? sf * pow2_near(delta * p.T_ref) : sf;
+            }
+            d.shell_scale[0][sh] = (float)sf;
+            d.shell_scale[1][sh] = (float)sg;
+            d.shell_inv_scale[0][sh] = (float)(1.0 / sf);
+            d.shell_inv_scale[1][sh] = (float)(1.0 / sg);
         }
         for (int i = 0; i < kQ; ++i) {
             const double wf = (double)d.shift_w[i], wg = (double)d.shift_w[kQ + i];
@@ -387,6 +400,25 @@ int lbm_create(const lbm_params *params, void *dev_arena, int64_t arena_bytes, v
         d.ref_mom[1] = (float)mom[1];
         d.ref_mom[2] = (float)mom[2];
         d.ref_energy = (float)ener;
+    }
+
+    // projection constants for FP32 arithmetic (rest weights per shell)
+    {
+        double W0 = 0, Wq = 0, Wqq = 0, W2 = 0;
+        for (int i = 0; i < kQ; ++i) {
+            const int cx = vel(i, 0), cy = vel(i, 1), cz = vel(i, 2);
+            const double q = cx * cx + cy * cy + cz * cz;
+            d.proj_w[shell(i)] = (float)rest[i];
+            W0 += rest[i];
+            Wq += rest[i] * q;
+            Wqq += rest[i] * q * q;
+            W2 += rest[i] * cx * cx;
+        }
+        const double det = W0 * Wqq - Wq * Wq;
+        d.proj_inv[0] = (float)(Wqq / det);
+        d.proj_inv[1] = (float)(-Wq / det);
+        d.proj_inv[2] = (float)(W0 / det);
+        d.proj_inv_w2 = (float)(1.0 / W2);
     }
 
     // obstacle links
@@ -499,6 +531,9 @@ int lbm_step(lbm_ctx *c, int32_t nsteps, lbm_step_stats *stats)
     stats->failed = h[2];
     stats->cold_restarts = h[3];
     for (int k = 0; k < 4; ++k) stats->alpha_hist[k] = h[4 + k];
+    stats->wave_iterations = h[8];
+    // every lane of a wave adds the wave's count once per wave-step
+    stats->waves = h[9];
     if (h[2] > 0) return fail(c, LBM_E_NEWTON, std::to_string(h[2]) + " cell updates did not converge");
     return LBM_OK;
 }

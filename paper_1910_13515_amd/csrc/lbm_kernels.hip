@@ -28,16 +28,56 @@ template <>
 struct StoreTraits<double> {
     using C = double;
     static constexpr bool kShift = false;
+    static constexpr bool kScale = false;
+    static constexpr int kWavesPerSimd = 1;  // FP64 arithmetic needs the full register file
 };
+
+// Global-memory pointers (address space 1): loads and stores then use a
+// uniform 64-bit base in SGPRs plus a 32-bit per-lane byte offset.
+using gbyte = char __attribute__((address_space(1)));
+using gcbyte = const char __attribute__((address_space(1)));
+
+template <class S>
+__device__ __forceinline__ S gload(gcbyte *base, uint32_t off)
+{
+    return *reinterpret_cast<const S __attribute__((address_space(1))) *>(base + off);
+}
+template <class S>
+__device__ __forceinline__ void gstore(gbyte *base, uint32_t off, S v)
+{
+    *reinterpret_cast<S __attribute__((address_space(1))) *>(base + off) = v;
+}
+
+// LDS parking of the gathered populations during the Newton solve: each lane
+// owns column threadIdx.x of a [78][256] array (no cross-lane sharing, so no
+// barriers).  Values are parked in the arithmetic type of the path.
+template <class C>
+struct Park {
+    C *base;  // &lds[0][threadIdx.x]
+    __device__ __forceinline__ void put(int i, C v) const { base[i * kBlockThreads] = v; }
+    __device__ __forceinline__ C get(int i) const { return base[i * kBlockThreads]; }
+};
+
+// Running moments of the gathered populations: mass, momentum, and the
+// energy sum f |xi|^2 + g (Sec. 3 and the first row of the Sec. 5 table).
+template <class C>
+struct MomentAcc {
+    C rho, j[3], e, sg;
+};
+
 template <>
 struct StoreTraits<float> {
     using C = float;
     static constexpr bool kShift = true;
+    static constexpr bool kScale = false;
+    static constexpr int kWavesPerSimd = 2;  // 256 registers per lane, LDS for the parked populations
 };
 template <>
 struct StoreTraits<_Float16> {
     using C = float;
     static constexpr bool kShift = true;
+    static constexpr bool kScale = true;  // deviations stored divided by a power of two per shell
+    static constexpr int kWavesPerSimd = 2;
 };
 
 // Coordinate of the pull source along one axis, for a cell at coordinate v
@@ -97,167 +137,210 @@ __device__ __forceinline__ int64_t wave_max(int64_t v)
     return v;
 }
 
-template <int I, class S, class C>
-__device__ __forceinline__ void gather_one(const SlotDesc &d, const S *src, int64_t cell, uint64_t links,
-                                           const int64_t (&X)[7], const int64_t (&Y)[7], const int64_t (&Z)[7],
-                                           C *hf, C *hg)
+// Gather of one opposite pair p (velocities a = 2p+1 with c_p and b = 2p+2
+// with -c_p) into a fluid cell.  Both populations are addressed from the base
+// of array a, so that a half-way bounce-back (which reads the cell's own
+// opposite population) stays a 32-bit offset from the same uniform base:
+//   f_a: from x - c_p, or when blocked f_b at the cell  (offset n + cell)
+//   f_b: from x + c_p, or when blocked f_a at the cell  (offset cell)
+template <int P, class S, class C>
+__device__ __forceinline__ void gather_pair(const SlotDesc &d, gcbyte *srcb, uint64_t nS64, uint32_t nS,
+                                            uint32_t cellS, uint64_t links, const uint32_t (&Xo)[7],
+                                            const uint32_t (&Yo)[7], const uint32_t (&Zo)[7], const Park<C> &pk,
+                                            MomentAcc<C> &acc)
 {
-    constexpr int cx = vel(I, 0), cy = vel(I, 1), cz = vel(I, 2);
-    int64_t idx = X[cx + 3] + Y[cy + 3] + Z[cz + 3];
-    int pop = I;
-    if constexpr (I != 0) {
-        if ((links >> I) & 1ull) {  // half-way bounce-back: own opposite population
-            idx = cell;
-            pop = opposite(I);
-        }
+    constexpr int a = 2 * P + 1, b = 2 * P + 2;
+    constexpr int cx = kPairVel[P][0], cy = kPairVel[P][1], cz = kPairVel[P][2];
+    uint32_t oa = Xo[cx + 3] + (Yo[cy + 3] + Zo[cz + 3]);
+    uint32_t ob = nS + (Xo[3 - cx] + (Yo[3 - cy] + Zo[3 - cz]));
+    oa = ((links >> a) & 1ull) ? nS + cellS : oa;
+    ob = ((links >> b) & 1ull) ? cellS : ob;
+    gcbyte *bf = srcb + (uint64_t)a * nS64;
+    gcbyte *bg = srcb + (uint64_t)(kQ + a) * nS64;
+    C fa = C(gload<S>(bf, oa)), fb = C(gload<S>(bf, ob));
+    C ga = C(gload<S>(bg, oa)), gb = C(gload<S>(bg, ob));
+    if constexpr (StoreTraits<S>::kScale) {
+        const C sf = C(d.shell_scale[0][shell(a)]), sg = C(d.shell_scale[1][shell(a)]);
+        fa *= sf;
+        fb *= sf;
+        ga *= sg;
+        gb *= sg;
     }
-    C vf = load_pop<S, C>(src, d.n, pop, idx);
-    C vg = load_pop<S, C>(src, d.n, kQ + pop, idx);
-    if constexpr (StoreTraits<S>::kShift) {
-        vf *= C(d.shift_scale[I]);
-        vg *= C(d.shift_scale[kQ + I]);
-    }
-    hf[I] = vf;
-    hg[I] = vg;
+    pk.put(a, fa);
+    pk.put(b, fb);
+    pk.put(kQ + a, ga);
+    pk.put(kQ + b, gb);
+    const C sp = fa + fb, ap = fa - fb;
+    acc.rho += sp;
+    acc.j[0] = Term<cx>::add(acc.j[0], ap);
+    acc.j[1] = Term<cy>::add(acc.j[1], ap);
+    acc.j[2] = Term<cz>::add(acc.j[2], ap);
+    acc.e = Term<pair_q(P)>::add(acc.e, sp);
+    acc.sg += ga + gb;
 }
 
-template <class S, class C, int... I>
-__device__ __forceinline__ void gather_all(const SlotDesc &d, const S *src, int64_t cell, uint64_t links,
-                                           const int64_t (&X)[7], const int64_t (&Y)[7], const int64_t (&Z)[7],
-                                           C *hf, C *hg, std::integer_sequence<int, I...>)
+template <class S, class C, int... P>
+__device__ __forceinline__ void gather_pairs(const SlotDesc &d, gcbyte *srcb, uint64_t nS64, uint32_t nS,
+                                             uint32_t cellS, uint64_t links, const uint32_t (&Xo)[7],
+                                             const uint32_t (&Yo)[7], const uint32_t (&Zo)[7], const Park<C> &pk,
+                                             MomentAcc<C> &acc, std::integer_sequence<int, P...>)
 {
-    (gather_one<I>(d, src, cell, links, X, Y, Z, hf, hg), ...);
+    (gather_pair<P, S, C>(d, srcb, nS64, nS, cellS, links, Xo, Yo, Zo, pk, acc), ...);
 }
 
-// eps contribution and BGK update of velocity I; stores the result
+// BGK update of velocity I for f and g; stores the result
 template <int I, class S, class C>
-__device__ __forceinline__ void relax_one(const SlotDesc &d, S *dst, int64_t cell, C rho, C dT, C omega,
-                                          C f0, const C *fp, const C *fm, const C *hf, const C *hg)
+__device__ __forceinline__ void relax_one(const SlotDesc &d, gbyte *dstb, uint64_t nS64, uint32_t cellS, C rho, C dT,
+                                          C omega, C f0, const C *fp, const C *fm, const Park<C> &pk)
 {
     const C feq = rho * feq_of<I>(f0, fp, fm);
     const C geq = dT * feq;
+    const C hf = pk.get(I), hg = pk.get(kQ + I);
     C of, og;
     if constexpr (StoreTraits<S>::kShift) {
         // deviations from the shift weights: D* = D + omega ((h_eq - w) - D)
-        const C df = hf[I], dg = hg[I];
-        of = df + omega * ((feq - C(d.shift_w[I])) - df);
-        og = dg + omega * ((geq - C(d.shift_w[kQ + I])) - dg);
-        of *= C(d.shift_inv_scale[I]);
-        og *= C(d.shift_inv_scale[kQ + I]);
+        of = hf + omega * ((feq - C(d.shift_w[I])) - hf);
+        og = hg + omega * ((geq - C(d.shift_w[kQ + I])) - hg);
+        if constexpr (StoreTraits<S>::kScale) {
+            of *= C(d.shell_inv_scale[0][shell(I)]);
+            og *= C(d.shell_inv_scale[1][shell(I)]);
+        }
     } else {
-        of = hf[I] + omega * (feq - hf[I]);
-        og = hg[I] + omega * (geq - hg[I]);
+        of = hf + omega * (feq - hf);
+        og = hg + omega * (geq - hg);
     }
-    dst[(int64_t)I * d.n + cell] = static_cast<S>(of);
-    dst[(int64_t)(kQ + I) * d.n + cell] = static_cast<S>(og);
+    gstore<S>(dstb + (uint64_t)I * nS64, cellS, static_cast<S>(of));
+    gstore<S>(dstb + (uint64_t)(kQ + I) * nS64, cellS, static_cast<S>(og));
 }
 
 template <class S, class C, int... I>
-__device__ __forceinline__ void relax_all(const SlotDesc &d, S *dst, int64_t cell, C rho, C dT, C omega, C f0,
-                                          const C *fp, const C *fm, const C *hf, const C *hg,
+__device__ __forceinline__ void relax_all(const SlotDesc &d, gbyte *dstb, uint64_t nS64, uint32_t cellS, C rho, C dT,
+                                          C omega, C f0, const C *fp, const C *fm, const Park<C> &pk,
                                           std::integer_sequence<int, I...>)
 {
-    (relax_one<I, S, C>(d, dst, cell, rho, dT, omega, f0, fp, fm, hf, hg), ...);
+    (relax_one<I, S, C>(d, dstb, nS64, cellS, rho, dT, omega, f0, fp, fm, pk), ...);
 }
 
 template <int I, class S, class C>
-__device__ __forceinline__ C eps_term(const SlotDesc &d, C rho, C f0, const C *fp, const C *fm, const C *hf)
+__device__ __forceinline__ C eps_term(const SlotDesc &d, C rho, C f0, const C *fp, const C *fm, const Park<C> &pk)
 {
     const C feq = rho * feq_of<I>(f0, fp, fm);
+    const C hf = pk.get(I);
     C diff;
-    if constexpr (StoreTraits<S>::kShift) diff = (C(d.shift_w[I]) - feq) + hf[I];
-    else diff = hf[I] - feq;
-    return fabs(diff) / feq;
+    if constexpr (StoreTraits<S>::kShift) diff = (C(d.shift_w[I]) - feq) + hf;
+    else diff = hf - feq;
+    return fabs(diff) * recip(feq);
 }
 
 template <class S, class C, int... I>
-__device__ __forceinline__ C eps_sum(const SlotDesc &d, C rho, C f0, const C *fp, const C *fm, const C *hf,
+__device__ __forceinline__ C eps_sum(const SlotDesc &d, C rho, C f0, const C *fp, const C *fm, const Park<C> &pk,
                                      std::integer_sequence<int, I...>)
 {
     C e = C(-0.0);
-    ((e += eps_term<I, S, C>(d, rho, f0, fp, fm, hf)), ...);
+    ((e += eps_term<I, S, C>(d, rho, f0, fp, fm, pk)), ...);
     return e;
 }
 
 using VelSeq = std::make_integer_sequence<int, kQ>;
 
-// One fluid cell: gather, moments, Newton, sensor, BGK, store.
+// One fluid cell: gather, moments, Newton, sensor, BGK, store.  (y, z) are
+// uniform across the wave; x is the lane's coordinate.
 template <class S>
 __device__ __forceinline__ void update_cell(const SlotDesc &d, const S *src, S *dst, int x, int y, int z,
-                                            int64_t cell, int64_t (&acc)[kStatWords])
+                                            uint32_t cell, const Park<typename StoreTraits<S>::C> &pk,
+                                            int64_t (&acc)[kStatWords])
 {
     using C = typename StoreTraits<S>::C;
     const uint64_t links = d.has_links ? d.links[cell] : 0ull;
     if (links >> 63) return;  // solid
 
-    int64_t X[7], Y[7], Z[7];
+    // byte offsets of the source coordinates x - c, c = -3..3, per axis
+    const uint32_t nx = (uint32_t)d.nx, nxy = (uint32_t)d.nx * (uint32_t)d.ny;
+    uint32_t Xo[7], Yo[7], Zo[7];
 #pragma unroll
     for (int c = -3; c <= 3; ++c) {
-        X[c + 3] = source_coord(x, c, d.nx, d.axis[0] == kAxisPeriodic, d.neumann_lo[0], d.neumann_hi[0]);
-        Y[c + 3] = (int64_t)source_coord(y, c, d.ny, d.axis[1] == kAxisPeriodic, d.neumann_lo[1], d.neumann_hi[1]) *
-                   d.nx;
-        Z[c + 3] = (int64_t)source_coord(z, c, d.nz, d.axis[2] == kAxisPeriodic, d.neumann_lo[2], d.neumann_hi[2]) *
-                   ((int64_t)d.nx * d.ny);
+        Xo[c + 3] = (uint32_t)source_coord(x, c, d.nx, d.axis[0] == kAxisPeriodic, d.neumann_lo[0], d.neumann_hi[0]) *
+                    (uint32_t)sizeof(S);
+        Yo[c + 3] = (uint32_t)source_coord(y, c, d.ny, d.axis[1] == kAxisPeriodic, d.neumann_lo[1], d.neumann_hi[1]) *
+                    nx * (uint32_t)sizeof(S);
+        Zo[c + 3] = (uint32_t)source_coord(z, c, d.nz, d.axis[2] == kAxisPeriodic, d.neumann_lo[2], d.neumann_hi[2]) *
+                    nxy * (uint32_t)sizeof(S);
     }
+    const uint64_t nS64 = (uint64_t)d.n * sizeof(S);
+    const uint32_t nS = (uint32_t)nS64;
+    const uint32_t cellS = cell * (uint32_t)sizeof(S);
+    gcbyte *srcb = (gcbyte *)src;
 
-    C hf[kQ], hg[kQ];
-    gather_all<S, C>(d, src, cell, links, X, Y, Z, hf, hg, VelSeq{});
-
-    // moments (Sec. 3; total energy 2 rho E = sum f |xi|^2 + sum g)
-    C rho, j[3], e;
+    // moments accumulate while the populations are parked (shifted storage
+    // starts from the sums of the shift weights)
+    MomentAcc<C> macc;
     if constexpr (StoreTraits<S>::kShift) {
-        rho = C(d.ref_mass);
-        j[0] = C(d.ref_mom[0]);
-        j[1] = C(d.ref_mom[1]);
-        j[2] = C(d.ref_mom[2]);
-        e = C(d.ref_energy);
+        macc.rho = C(d.ref_mass);
+        macc.j[0] = C(d.ref_mom[0]);
+        macc.j[1] = C(d.ref_mom[1]);
+        macc.j[2] = C(d.ref_mom[2]);
+        macc.e = C(d.ref_energy);
     } else {
-        rho = C(-0.0);
-        j[0] = j[1] = j[2] = C(-0.0);
-        e = C(-0.0);
+        macc.rho = C(-0.0);
+        macc.j[0] = macc.j[1] = macc.j[2] = C(-0.0);
+        macc.e = C(-0.0);
     }
     {
-        C sg = hg[0];
-        rho += hf[0];
-#pragma unroll
-        for (int p = 0; p < kPairs; ++p) {
-            const C sp = hf[2 * p + 1] + hf[2 * p + 2];
-            const C ap = hf[2 * p + 1] - hf[2 * p + 2];
-            rho += sp;
-            j[0] += C(kPairVel[p][0]) * ap;
-            j[1] += C(kPairVel[p][1]) * ap;
-            j[2] += C(kPairVel[p][2]) * ap;
-            e += C(pair_q(p)) * sp;
-            sg += hg[2 * p + 1] + hg[2 * p + 2];
+        C f0v = C(gload<S>(srcb, cellS));
+        C g0v = C(gload<S>(srcb + (uint64_t)kQ * nS64, cellS));
+        if constexpr (StoreTraits<S>::kScale) {
+            f0v *= C(d.shell_scale[0][0]);
+            g0v *= C(d.shell_scale[1][0]);
         }
-        e += sg;
+        pk.put(0, f0v);
+        pk.put(kQ, g0v);
+        macc.rho += f0v;
+        macc.sg = g0v;
     }
-    C u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
-    const C uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    const C T = (e - rho * uu) / (C(d.two_cv) * rho);
-
-    C m[kM];
-    mb_targets(u, T, m);
+    gather_pairs<S, C>(d, srcb, nS64, nS, cellS, links, Xo, Yo, Zo, pk, macc, PairSeq{});
+    // keep the parked values out of registers across the solve
+    __asm__ volatile("" ::: "memory");
+    const C rho = macc.rho;
+    const C j[3] = {macc.j[0], macc.j[1], macc.j[2]};
+    const C e = macc.e + macc.sg;
 
     C lam[kM];
-    C *lam_buf = static_cast<C *>(d.lam);
+    gbyte *lamb = (gbyte *)d.lam;
+    const uint64_t nC64 = (uint64_t)d.n * sizeof(C);
+    const uint32_t cellC = cell * (uint32_t)sizeof(C);
 #pragma unroll
-    for (int k = 0; k < kM; ++k) lam[k] = lam_buf[(int64_t)k * d.n + cell];
+    for (int k = 0; k < kM; ++k) lam[k] = gload<C>(lamb + (uint64_t)k * nC64, cellC);
+
+    // correctly rounded divisions (an approximate reciprocal here would bias
+    // T, and with it the total energy, by the same sign every step)
+    C u[3];
+    u[0] = j[0] / rho;
+    u[1] = j[1] / rho;
+    u[2] = j[2] / rho;
+    const C T = (e - rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2])) / (C(d.two_cv) * rho);
 
     C f0, fp[kPairs], fm[kPairs];
     int iters = 0;
-    const int status = solve_multipliers<C>(m, u, T, lam, f0, fp, fm, C(d.tol), d.maxit, d.maxit_cold, iters);
+    C resid[5];
+    const int status = solve_multipliers<C>(u, T, lam, f0, fp, fm, C(d.tol), d.maxit, d.maxit_cold, iters, resid);
+    if constexpr (sizeof(C) == 4) {
+        // FP32 arithmetic stops at a tolerance far above FP64's; make the
+        // collision invariants exact so that the bias of the last Newton
+        // step (its mass and energy residuals are positive) does not
+        // accumulate over time steps
+        project_invariants(f0, fp, fm, resid, d.proj_w, d.proj_inv, d.proj_inv_w2, PairSeq{});
+    }
 
     // Knudsen sensor over f (Eq. eq:DeltaAvg) and relaxation branch (Eq. eq:alpha)
-    const C eps = eps_sum<S, C>(d, rho, f0, fp, fm, hf, VelSeq{}) / C(kQ);
+    const C eps = eps_sum<S, C>(d, rho, f0, fp, fm, pk, VelSeq{}) * C(1.0 / kQ);
     int br = 0;
     if (d.kn_relax) br = (eps < C(1e-2)) ? 0 : (eps < C(1e-1)) ? 1 : (eps < C(1)) ? 2 : 3;
     const C omega = C(br == 0 ? d.omega[0] : br == 1 ? d.omega[1] : br == 2 ? d.omega[2] : d.omega[3]);
     const C dT = C(d.delta) * T;
 
-    relax_all<S, C>(d, dst, cell, rho, dT, omega, f0, fp, fm, hf, hg, VelSeq{});
+    relax_all<S, C>(d, (gbyte *)dst, nS64, cellS, rho, dT, omega, f0, fp, fm, pk, VelSeq{});
 #pragma unroll
-    for (int k = 0; k < kM; ++k) lam_buf[(int64_t)k * d.n + cell] = lam[k];
+    for (int k = 0; k < kM; ++k) gstore<C>(lamb + (uint64_t)k * nC64, cellC, lam[k]);
 
     acc[0] += iters;
     acc[1] = iters > acc[1] ? iters : acc[1];
@@ -282,16 +365,19 @@ __device__ __forceinline__ int find_slot(const SlotTable *tab, int b)
 // (a multiple of 8 blocks) is persistent: blocks stride over the logical
 // blocks of all slots, each XCD over its own contiguous range.
 template <class S>
-__global__ __launch_bounds__(kBlockThreads) void step_kernel(const SlotTable *__restrict__ tab, int j,
+__global__ __launch_bounds__(kBlockThreads, StoreTraits<S>::kWavesPerSimd) void step_kernel(const SlotTable *__restrict__ tab, int j,
                                                              int64_t *__restrict__ stats)
 {
-    int64_t acc[kStatWords] = {0, 0, 0, 0, 0, 0, 0, 0};
+    using C = typename StoreTraits<S>::C;
+    __shared__ C park[2 * kQ * kBlockThreads];
+    const Park<C> pk{park + threadIdx.x};
+    int64_t acc[kStatWords] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int total = tab->total_blocks;
     const int xcd = blockIdx.x & 7;
     const int per_xcd = gridDim.x >> 3;
     const int lo = (int)(((int64_t)total * xcd) >> 3);
     const int hi = (int)(((int64_t)total * (xcd + 1)) >> 3);
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     for (int b = lo + (int)(blockIdx.x >> 3); b < hi; b += per_xcd) {
         const int s = find_slot(tab, b);
@@ -300,17 +386,25 @@ __global__ __launch_bounds__(kBlockThreads) void step_kernel(const SlotTable *__
         const int64_t seg = (int64_t)(b - tab->block_start[s]) * kWavesPerBlock + wave;
         if (seg >= d.segments) continue;
         const int segx = (int)(seg % d.nsegx);
-        const int64_t row = seg / d.nsegx;
-        const int y = (int)(row % d.ny);
-        const int z = (int)(row / d.ny);
+        const int row = (int)(seg / d.nsegx);
+        const int y = row % d.ny;
+        const int z = row / d.ny;
         const int x = segx * kSegment + lane;
-        if (x >= d.nx) continue;
-        if (!is_fluid_coord(d, x, y, z)) continue;
-        const int par = (d.parity0 + j) & 1;
-        const S *src = static_cast<const S *>(d.buf[par]);
-        S *dst = static_cast<S *>(d.buf[par ^ 1]);
-        const int64_t cell = (int64_t)x + (int64_t)d.nx * ((int64_t)y + (int64_t)d.ny * z);
-        update_cell<S>(d, src, dst, x, y, z, cell, acc);
+        int64_t it_cell = 0;
+        if (x < d.nx && is_fluid_coord(d, x, y, z)) {
+            const int par = (d.parity0 + j) & 1;
+            const S *src = static_cast<const S *>(d.buf[par]);
+            S *dst = static_cast<S *>(d.buf[par ^ 1]);
+            const uint32_t cell = (uint32_t)x + (uint32_t)d.nx * ((uint32_t)y + (uint32_t)d.ny * (uint32_t)z);
+            const int64_t it_before = acc[0];
+            update_cell<S>(d, src, dst, x, y, z, cell, pk, acc);
+            it_cell = acc[0] - it_before;
+        }
+        // per-wave cost: the wave runs as many updates as its slowest cell
+        // (all 64 lanes are converged here)
+        const int64_t wmax = wave_max(it_cell);
+        acc[8] += lane == 0 ? wmax : 0;
+        acc[9] += lane == 0 ? 1 : 0;
     }
     if (stats) {
         int64_t red[kStatWords];
@@ -338,12 +432,12 @@ __global__ __launch_bounds__(256) void init_kernel(SlotDesc d, const double *__r
     const double rho = fields[cell];
     const double u[3] = {fields[d.n + cell], fields[2 * d.n + cell], fields[3 * d.n + cell]};
     const double T = fields[4 * d.n + cell];
-    double m[kM], lam[kM], f0, fp[kPairs], fm[kPairs];
-    mb_targets(u, T, m);
+    double lam[kM], f0, fp[kPairs], fm[kPairs];
     cold_guess(u, T, lam);
     int iters = 0;
     const int maxit = d.maxit_cold;
-    const int st = solve_multipliers<double>(m, u, T, lam, f0, fp, fm, d.tol, maxit, maxit, iters);
+    double resid[5];
+    const int st = solve_multipliers<double>(u, T, lam, f0, fp, fm, d.tol, maxit, maxit, iters, resid);
     if (st == kFailed) atomicAdd(failed, 1ull);
     const double dT = d.delta * T;
     S *b0 = static_cast<S *>(d.buf[0]);
@@ -355,8 +449,8 @@ __global__ __launch_bounds__(256) void init_kernel(SlotDesc d, const double *__r
         const double geq = dT * feq;
         double vf = feq, vg = geq;
         if constexpr (StoreTraits<S>::kShift) {
-            vf = (feq - (double)d.shift_w[i]) * (double)d.shift_inv_scale[i];
-            vg = (geq - (double)d.shift_w[kQ + i]) * (double)d.shift_inv_scale[kQ + i];
+            vf = (feq - (double)d.shift_w[i]) * (double)d.shell_inv_scale[0][shell(i)];
+            vg = (geq - (double)d.shift_w[kQ + i]) * (double)d.shell_inv_scale[1][shell(i)];
         }
         const S sf = static_cast<S>(vf), sg = static_cast<S>(vg);
         b0[(int64_t)i * d.n + cell] = sf;
@@ -376,11 +470,11 @@ __global__ void single_equilibrium_kernel(double rho, double ux, double uy, doub
 {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     const double u[3] = {ux, uy, uz};
-    double m[kM], lam[kM], f0, fp[kPairs], fm[kPairs];
-    mb_targets(u, T, m);
+    double lam[kM], f0, fp[kPairs], fm[kPairs];
     cold_guess(u, T, lam);
     int iters = 0;
-    *status = solve_multipliers<double>(m, u, T, lam, f0, fp, fm, tol, maxit, maxit, iters);
+    double resid[5];
+    *status = solve_multipliers<double>(u, T, lam, f0, fp, fm, tol, maxit, maxit, iters, resid);
     for (int i = 0; i < kQ; ++i)
         out[i] = rho * ((i == 0) ? f0 : (((i - 1) & 1) == 0 ? fp[(i - 1) >> 1] : fm[(i - 1) >> 1]));
     for (int k = 0; k < kM; ++k) out[kQ + k] = lam[k];
@@ -424,8 +518,8 @@ __global__ __launch_bounds__(256) void moments_kernel(SlotDesc d, int parity, do
                 double vf = (double)b[(int64_t)i * d.n + src];
                 double vg = (double)b[(int64_t)(kQ + i) * d.n + src];
                 if constexpr (StoreTraits<S>::kShift) {
-                    vf = (double)d.shift_w[i] + vf * (double)d.shift_scale[i];
-                    vg = (double)d.shift_w[kQ + i] + vg * (double)d.shift_scale[kQ + i];
+                    vf = (double)d.shift_w[i] + vf * (double)d.shell_scale[0][shell(i)];
+                    vg = (double)d.shift_w[kQ + i] + vg * (double)d.shell_scale[1][shell(i)];
                 }
                 const int cx = vel(i, 0), cy = vel(i, 1), cz = vel(i, 2);
                 r += vf;
@@ -486,7 +580,7 @@ __global__ __launch_bounds__(256) void reduce_stats_kernel(const int64_t *__rest
                                                            int64_t *__restrict__ out)
 {
     __shared__ int64_t red[kStatWords][256];
-    int64_t t[kStatWords] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t t[kStatWords] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int w = threadIdx.x; w < nwaves; w += blockDim.x)
         for (int k = 0; k < kStatWords; ++k) {
             const int64_t v = partial[(int64_t)w * kStatWords + k];
@@ -523,7 +617,8 @@ __global__ void decode_pop_kernel(SlotDesc d, int parity, int pop, double *__res
     if (c >= d.n) return;
     const S *b = static_cast<const S *>(d.buf[parity]);
     double v = (double)b[(int64_t)pop * d.n + c];
-    if constexpr (StoreTraits<S>::kShift) v = (double)d.shift_w[pop] + v * (double)d.shift_scale[pop];
+    if constexpr (StoreTraits<S>::kShift)
+        v = (double)d.shift_w[pop] + v * (double)d.shell_scale[pop >= kQ][shell(pop % kQ)];
     out[c] = v;
 }
 
@@ -533,7 +628,8 @@ __global__ void encode_pop_kernel(SlotDesc d, int pop, const double *__restrict_
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= d.n) return;
     double v = in[c];
-    if constexpr (StoreTraits<S>::kShift) v = (v - (double)d.shift_w[pop]) * (double)d.shift_inv_scale[pop];
+    if constexpr (StoreTraits<S>::kShift)
+        v = (v - (double)d.shift_w[pop]) * (double)d.shell_inv_scale[pop >= kQ][shell(pop % kQ)];
     const S s = static_cast<S>(v);
     static_cast<S *>(d.buf[0])[(int64_t)pop * d.n + c] = s;
     static_cast<S *>(d.buf[1])[(int64_t)pop * d.n + c] = s;

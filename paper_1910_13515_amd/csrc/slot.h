@@ -43,13 +43,20 @@ struct SlotDesc {
     void *lam;               // multipliers [13][n] in the arithmetic type
     const uint64_t *links;   // per cell: bit i = link i blocked (half-way bounce-back), bit 63 = solid
     int64_t *stats;          // per-wave partial statistics (8 x int64 per wave of the launch grid)
-    // shifted storage: h_i = w_i + scale_i * stored_i (f: 0..38, g: 39..77)
+    // shifted storage: h_i = w_i + scale * stored_i (f: 0..38, g: 39..77);
+    // FP16 only: scale is a power of two per velocity shell |xi|^2 in
+    // {0, 1, 3, 4, 8, 9} (index 0..5), for f (row 0) and g (row 1)
     float shift_w[78];
-    float shift_scale[78];
-    float shift_inv_scale[78];
+    float shell_scale[2][6];
+    float shell_inv_scale[2][6];
     // sums of the shift weights: mass, momentum (3), energy sum f|xi|^2 + g
     float ref_mass, ref_mom[3], ref_energy;
-    float pad1[3];
+    // FP32 arithmetic: projection of the invariants' residual (rest-state
+    // weights per shell at T_ref per unit density, inverse of the 2x2
+    // mass/energy block {i00, i01, i11}, and 1 / sum_i w_i xi_x^2)
+    float proj_w[6];
+    float proj_inv[3];
+    float proj_inv_w2;
 };
 
 struct SlotTable {
@@ -64,7 +71,7 @@ inline constexpr std::size_t slot_table_bytes(int nslots)
     return sizeof(SlotTable) + sizeof(SlotDesc) * (nslots > 1 ? nslots - 1 : 0);
 }
 
-constexpr int kStatWords = 8;  // iterations, max, failed, cold, hist[4]
+constexpr int kStatWords = 10;  // iterations, max, failed, cold, hist[4], wave iterations, waves
 
 // outcome of a cell's Newton solve
 enum NewtonStatus : int { kConverged = 0, kConvergedCold = 1, kFailed = 2 };

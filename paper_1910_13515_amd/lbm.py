@@ -56,6 +56,7 @@ class lbm_step_stats(ctypes.Structure):
     _fields_ = [
         ("cell_updates", ctypes.c_int64), ("iterations", ctypes.c_int64), ("max_iterations", ctypes.c_int64),
         ("failed", ctypes.c_int64), ("cold_restarts", ctypes.c_int64), ("alpha_hist", ctypes.c_int64 * 4),
+        ("wave_iterations", ctypes.c_int64), ("waves", ctypes.c_int64),
     ]
 
 

@@ -1,0 +1,102 @@
+"""Reduced-precision storage (FP32- and FP16-shifted populations, FP32
+arithmetic) against the FP64 oracle on the GPU.
+
+The tolerances follow from the arithmetic: FP32 carries 24 significant bits
+(unit round-off 6e-8) and its Newton solve stops at 2e-6 of the largest
+target moment; FP16 deviations carry 11 bits (4.9e-4 relative to the
+deviation from the shift weights).  Each test prints its measured errors."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from _helpers import max_rel, moment_error, oracle_state  # noqa: E402
+
+from paper_1910_13515_amd import inputs  # noqa: E402
+
+# bars per storage mode: (single-step populations rel. to max, single-step
+# moments, Sod plateau L1 of rho relative to the FP64 run)
+BARS = {"fp32s": (1e-5, 3e-5, 2e-4), "fp16s": (3e-4, 1e-3, 5e-3)}
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1910_13515_amd import lbm as L
+    L.load()
+    return L
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("storage", ["fp32s", "fp16s"])
+@pytest.mark.parametrize("shape", [(4, 4, 4), (70, 5, 4)])
+def test_single_step_from_oracle_state(orc, lbm, storage, shape):
+    f, g, lam = oracle_state(orc, shape, 1.4, seed=29, amplitudes=(1e-3, 1e-2), spread=0.3)
+    o = orc.Oracle(*shape, gamma=1.4, tau=0.55, kn_relax=True, newton_tol=1e-13)
+    o.set_state(f, g, lam)
+    o.step(1)
+    s = lbm.Solver(shape, storage=storage, gamma=1.4, tau=0.55, kn_relax=True)
+    s.set_state(f, g, lam)
+    st = s.step(1, stats=True)
+    fg, gg, _ = s.get_state()
+    m, t = s.moments()
+    mo, to = o.moments()
+    ef, eg = max_rel(fg, o.f), max_rel(gg, o.g)
+    em = moment_error(m, mo)
+    _log(f"{storage} {shape}: populations f {ef:.2e} g {eg:.2e}; moments rho/u/T {em[0]:.2e}/{em[1]:.2e}/{em[2]:.2e};"
+         f" newton it/cell {st.iterations / st.cell_updates:.2f}, failed {st.failed}")
+    bar_pop, bar_mom, _ = BARS[storage]
+    assert st.failed == 0
+    assert ef < bar_pop and eg < bar_pop
+    assert max(em) < bar_mom
+    s.close()
+
+
+@pytest.mark.parametrize("storage", ["fp32s", "fp16s"])
+def test_sod_against_fp64(orc, lbm, storage):
+    """Config: Sod tube 400x1x1 with equilibrium ends, 150 steps, tau 0.57
+    (plain BGK) and tau 0.5 (Knudsen-dependent)."""
+    nx = 400
+    fields = inputs.sod_fields(nx, temp_scale=0.5)
+    for tau, kn in ((0.57, False), (0.5, True)):
+        kw = dict(gamma=1.4, tau=tau, kn_relax=kn, faces=(1, 1, 0, 0, 0, 0))
+        o = orc.Oracle(nx, 1, 1, newton_tol=1e-12, **kw)
+        o.init(*fields)
+        o.step(150)
+        s = lbm.Solver((nx, 1, 1), fields=fields, storage=storage, **kw)
+        st = s.step(150, stats=True)
+        m, _ = s.moments()
+        mo, _ = o.moments()
+        l1 = np.abs(m[0] - mo[0]).mean() / np.abs(mo[0]).mean()
+        linf = np.abs(m[0] - mo[0]).max()
+        _log(f"{storage} sod tau={tau} kn={kn}: rho L1 rel {l1:.2e}, Linf {linf:.2e}, failed {st.failed}")
+        assert st.failed == 0
+        assert l1 < BARS[storage][2]
+        s.close()
+
+
+@pytest.mark.parametrize("storage", ["fp32s", "fp16s"])
+def test_mass_conservation_reduced_precision(lbm, storage):
+    """Periodic TGV 32^3: the FP64 totals of the stored state drift only by
+    storage rounding."""
+    n = 32
+    U = 0.5 * np.sqrt(1.4 * 0.5)
+    fields = inputs.taylor_green_fields(n, U, 0.5)
+    s = lbm.Solver((n, n, n), fields=fields, storage=storage, gamma=1.4, mach=0.5, reynolds=1600.0,
+                   length_ref=n / (2 * np.pi), T_ref=0.5, u_dir=(1, 0, 0), kn_relax=True)
+    _, t0 = s.moments(fields=False)
+    s.step(100)
+    _, t = s.moments(fields=False)
+    drift = abs(t[0] - t0[0]) / t0[0]
+    edrift = abs(t[4] - t0[4]) / t0[4]
+    _log(f"{storage} tgv32 100 steps: mass drift {drift:.2e}, energy drift {edrift:.2e}")
+    bound = 2e-6 if storage == "fp32s" else 2e-5
+    assert drift < bound and edrift < bound
+    s.close()
