@@ -75,6 +75,8 @@ std::string validate(const lbm_params *p)
     if (p->storage < LBM_STORE_FP64 || p->storage > LBM_STORE_FP16_SHIFTED) return "unknown storage mode";
     // the kernels address two population arrays from one base with 32-bit byte offsets
     if (2 * n * storage_bytes(p->storage) >= ((int64_t)1 << 32)) return "grid too large for this storage mode";
+    // FP32: row stores address four population arrays from one base
+    if (p->storage == LBM_STORE_FP32_SHIFTED && 4 * n * 4 >= ((int64_t)1 << 32)) return "grid too large for FP32 storage";
     if (p->shift_ref < 0 || p->shift_ref > 1) return "shift_ref must be 0 or 1";
     const int dims[3] = {p->nx, p->ny, p->nz};
     for (int a = 0; a < 3; ++a) {

@@ -20,6 +20,12 @@
 #include "equilibrium.h"
 #include "slot.h"
 
+// FP32-shifted storage: 1 = step_kernel_f32 (gather into LDS by direct
+// loads, 16-byte row stores); 0 = step_kernel<float>
+#ifndef LBM_FP32_DMA
+#define LBM_FP32_DMA 1
+#endif
+
 namespace lbm13 {
 
 template <class S>
@@ -419,6 +425,229 @@ __global__ __launch_bounds__(kBlockThreads, StoreTraits<S>::kWavesPerSimd) void 
 }
 
 // ---------------------------------------------------------------------------
+// FP32-shifted step: the gather goes global -> LDS directly (no registers,
+// per-lane addresses, so wrap, clamps and bounce-back are unchanged), and the
+// results leave LDS as 16-byte-per-lane stores of whole 64-cell rows.  Lanes
+// of non-fluid cells gather their own values, so that a row can be stored
+// whole without changing them.  Two waves per SIMD; each wave touches only
+// its own LDS columns, so no barriers are needed.
+namespace f32 {
+
+using lds_float = float __attribute__((address_space(3)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// s_waitcnt vmcnt(0) (gfx9 encoding, expcnt and lgkmcnt at their maxima): the
+// compiler does not track loads into LDS, so reads of gathered rows wait here
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+__device__ __forceinline__ void dma4(gcbyte *gaddr, lds_float *row_base)
+{
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)gaddr,
+                                     (void __attribute__((address_space(3))) *)row_base, 4, 0, 0);
+}
+
+__device__ __forceinline__ float uniform(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+
+// gather of one cell's 78 values into the wave's LDS rows (row i at
+// rows + i*256); copy = the cell's own values
+__device__ __forceinline__ void gather(const SlotDesc &d, gcbyte *srcb, int x, int y, int z, uint32_t cell,
+                                       uint64_t links, bool copy, lds_float *rows)
+{
+    const uint64_t nS64 = (uint64_t)d.n * 4;
+    const uint32_t nS = (uint32_t)nS64;
+    const uint32_t cellS = cell * 4u;
+    const uint32_t nx = (uint32_t)d.nx, nxy = (uint32_t)d.nx * (uint32_t)d.ny;
+    uint32_t Xo[7], Yo[7], Zo[7];
+#pragma unroll
+    for (int c = -3; c <= 3; ++c) {
+        Xo[c + 3] = (uint32_t)source_coord(x, c, d.nx, d.axis[0] == kAxisPeriodic, d.neumann_lo[0], d.neumann_hi[0]) * 4u;
+        Yo[c + 3] = (uint32_t)source_coord(y, c, d.ny, d.axis[1] == kAxisPeriodic, d.neumann_lo[1], d.neumann_hi[1]) * nx * 4u;
+        Zo[c + 3] = (uint32_t)source_coord(z, c, d.nz, d.axis[2] == kAxisPeriodic, d.neumann_lo[2], d.neumann_hi[2]) * nxy * 4u;
+    }
+    dma4(srcb + cellS, rows);
+    dma4(srcb + (uint64_t)kQ * nS64 + cellS, rows + kQ * kBlockThreads);
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p) {
+        const int a = 2 * p + 1, b = 2 * p + 2;
+        const int cx = kPairVel[p][0], cy = kPairVel[p][1], cz = kPairVel[p][2];
+        uint32_t oa = Xo[cx + 3] + (Yo[cy + 3] + Zo[cz + 3]);
+        uint32_t ob = nS + (Xo[3 - cx] + (Yo[3 - cy] + Zo[3 - cz]));
+        oa = ((links >> a) & 1ull) ? nS + cellS : oa;
+        ob = ((links >> b) & 1ull) ? cellS : ob;
+        oa = copy ? cellS : oa;
+        ob = copy ? nS + cellS : ob;
+        gcbyte *bf = srcb + (uint64_t)a * nS64;
+        gcbyte *bg = srcb + (uint64_t)(kQ + a) * nS64;
+        dma4(bf + oa, rows + a * kBlockThreads);
+        dma4(bf + ob, rows + b * kBlockThreads);
+        dma4(bg + oa, rows + (kQ + a) * kBlockThreads);
+        dma4(bg + ob, rows + (kQ + b) * kBlockThreads);
+    }
+}
+
+// moments, Newton, sensor and relaxation of one fluid cell whose gathered
+// values sit in LDS; the results replace them
+__device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const Park<float> &pk,
+                                        int64_t (&acc)[kStatWords])
+{
+    using C = float;
+    using S = float;
+    C rho = C(d.ref_mass), j0 = C(d.ref_mom[0]), j1 = C(d.ref_mom[1]), j2 = C(d.ref_mom[2]), e = C(d.ref_energy);
+    C sg = pk.get(kQ);
+    rho += pk.get(0);
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p) {
+        const C fa = pk.get(2 * p + 1), fb = pk.get(2 * p + 2);
+        const C sp = fa + fb, ap = fa - fb;
+        rho += sp;
+        j0 += C(kPairVel[p][0]) * ap;
+        j1 += C(kPairVel[p][1]) * ap;
+        j2 += C(kPairVel[p][2]) * ap;
+        e += C(pair_q(p)) * sp;
+        sg += pk.get(kQ + 2 * p + 1) + pk.get(kQ + 2 * p + 2);
+    }
+    e += sg;
+    // the gathered values are read again after the solve, not kept in registers
+    __asm__ volatile("" ::: "memory");
+    C u[3];
+    u[0] = j0 / rho;
+    u[1] = j1 / rho;
+    u[2] = j2 / rho;
+    const C T = (e - rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2])) / (C(d.two_cv) * rho);
+
+    gbyte *lamb = (gbyte *)d.lam;
+    const uint64_t nS64 = (uint64_t)d.n * 4;
+    const uint32_t cellS = cell * 4u;
+    C lam[kM];
+#pragma unroll
+    for (int k = 0; k < kM; ++k) lam[k] = gload<C>(lamb + (uint64_t)k * nS64, cellS);
+
+    C f0, fp[kPairs], fm[kPairs];
+    int iters = 0;
+    C resid[5];
+    const int status = solve_multipliers<C>(u, T, lam, f0, fp, fm, C(d.tol), d.maxit, d.maxit_cold, iters, resid);
+    project_invariants(f0, fp, fm, resid, d.proj_w, d.proj_inv, d.proj_inv_w2, PairSeq{});
+
+    const C eps = eps_sum<S, C>(d, rho, f0, fp, fm, pk, VelSeq{}) * C(1.0 / kQ);
+    int br = 0;
+    if (d.kn_relax) br = (eps < C(1e-2)) ? 0 : (eps < C(1e-1)) ? 1 : (eps < C(1)) ? 2 : 3;
+    const C o0 = uniform(C(d.omega[0])), o1 = uniform(C(d.omega[1])), o2 = uniform(C(d.omega[2])),
+            o3 = uniform(C(d.omega[3]));
+    C omega = o0;
+    omega = br == 1 ? o1 : omega;
+    omega = br == 2 ? o2 : omega;
+    omega = br == 3 ? o3 : omega;
+    const C dT = C(d.delta) * T;
+    __asm__ volatile("" ::: "memory");
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const C e_i = (i == 0) ? f0 : (((i - 1) & 1) == 0 ? fp[(i - 1) >> 1] : fm[(i - 1) >> 1]);
+        const C feq = rho * e_i;
+        const C geq = dT * feq;
+        const C hf = pk.get(i), hg = pk.get(kQ + i);
+        pk.put(i, hf + omega * ((feq - C(d.shift_w[i])) - hf));
+        pk.put(kQ + i, hg + omega * ((geq - C(d.shift_w[kQ + i])) - hg));
+    }
+#pragma unroll
+    for (int k = 0; k < kM; ++k) gstore<C>(lamb + (uint64_t)k * nS64, cellS, lam[k]);
+
+    acc[0] += iters;
+    acc[1] = iters > acc[1] ? iters : acc[1];
+    acc[2] += status == kFailed;
+    acc[3] += status == kConvergedCold;
+    acc[4] += br == 0;
+    acc[5] += br == 1;
+    acc[6] += br == 2;
+    acc[7] += br == 3;
+}
+
+}  // namespace f32
+
+__global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f32(const SlotTable *__restrict__ tab, int j,
+                                                                   int64_t *__restrict__ stats)
+{
+    __shared__ float park[2 * kQ * kBlockThreads];
+    const Park<float> pk{park + threadIdx.x};
+    int64_t acc[kStatWords] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int total = tab->total_blocks;
+    const int xcd = blockIdx.x & 7;
+    const int per_xcd = gridDim.x >> 3;
+    const int lo = (int)(((int64_t)total * xcd) >> 3);
+    const int hi = (int)(((int64_t)total * (xcd + 1)) >> 3);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    f32::lds_float *rows = (f32::lds_float *)park + wave * kSegment;
+    for (int b = lo + (int)(blockIdx.x >> 3); b < hi; b += per_xcd) {
+        const int s = find_slot(tab, b);
+        const SlotDesc &d = tab->slot[s];
+        if (j >= d.steps_todo) continue;
+        const int64_t seg = (int64_t)(b - tab->block_start[s]) * kWavesPerBlock + wave;
+        if (seg >= d.segments) continue;
+        const int segx = (int)(seg % d.nsegx);
+        const int row = (int)(seg / d.nsegx);
+        const int y = row % d.ny;
+        const int z = row / d.ny;
+        const int x = segx * kSegment + lane;
+        const uint32_t cell0 = (uint32_t)(segx * kSegment) + (uint32_t)d.nx * (uint32_t)row;
+        const bool full = (segx * kSegment + kSegment <= d.nx) && (d.nx % 4 == 0);
+        const bool in_grid = x < d.nx;
+        const uint32_t cell = cell0 + (uint32_t)lane;
+        const int par = (d.parity0 + j) & 1;
+        gcbyte *srcb = (gcbyte *)d.buf[par];
+        gbyte *dstb = (gbyte *)d.buf[par ^ 1];
+        bool fluid = in_grid && is_fluid_coord(d, x, y, z);
+        uint64_t links = 0;
+        if (fluid && d.has_links) links = d.links[cell];
+        if (links >> 63) fluid = false;  // solid cells pass through unchanged
+        if (in_grid) f32::gather(d, srcb, x, y, z, cell, links, !fluid, rows);
+        f32::wait_vmem();
+        int64_t it_cell = 0;
+        if (fluid) {
+            const int64_t before = acc[0];
+            f32::collide(d, cell, pk, acc);
+            it_cell = acc[0] - before;
+        }
+        const int64_t wmax = wave_max(it_cell);
+        acc[8] += lane == 0 ? wmax : 0;
+        acc[9] += lane == 0 ? 1 : 0;
+        // store the wave's rows
+        const uint64_t nS64 = (uint64_t)d.n * 4;
+        const float *col = park + wave * kSegment;
+        if (full) {
+            // lanes 16r..16r+15 store row i0 + r, 4 cells each: one uniform
+            // base per group of 4 rows and one 32-bit lane offset
+            const int r = lane >> 4, c4 = (lane & 15) * 4;
+            uint32_t voff = (uint32_t)r * (uint32_t)nS64 + (cell0 + (uint32_t)c4) * 4u;
+            const float *lcol = col + r * kBlockThreads + c4;
+            __asm__ volatile("" : "+v"(voff));
+#pragma unroll
+            for (int i0 = 0; i0 < 2 * kQ; i0 += 4) {
+                if (i0 + r < 2 * kQ) {
+                    const f32::v4f v = *reinterpret_cast<const f32::v4f *>(lcol + i0 * kBlockThreads);
+                    *reinterpret_cast<f32::v4f __attribute__((address_space(1))) *>(dstb + (uint64_t)i0 * nS64 + voff) = v;
+                }
+            }
+        } else if (in_grid) {
+#pragma unroll
+            for (int i = 0; i < 2 * kQ; ++i) gstore<float>(dstb + (uint64_t)i * nS64, cell * 4u, col[i * kBlockThreads + lane]);
+        }
+    }
+    if (stats) {
+        int64_t red[kStatWords];
+#pragma unroll
+        for (int k = 0; k < kStatWords; ++k) red[k] = (k == 1) ? wave_max(acc[k]) : wave_sum(acc[k]);
+        if (lane == 0) {
+            int64_t *p = stats + ((int64_t)blockIdx.x * kWavesPerBlock + wave) * kStatWords;
+#pragma unroll
+            for (int k = 0; k < kStatWords; ++k) p[k] = (k == 1) ? (red[k] > p[k] ? red[k] : p[k]) : p[k] + red[k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Initial state: the equilibrium of the given fields, cold-started in FP64.
 // fields: rho[n], ux[n], uy[n], uz[n], T[n] (FP64).  Writes both buffers and
 // the multipliers.  failed (int64) counts cells whose Newton did not converge.
@@ -664,7 +893,13 @@ hipError_t launch_step(int storage, const SlotTable *tab, int grid, int j, int64
 {
     switch (storage) {
     case kStoreF64: return launch_step_t<double>(tab, grid, j, stats, st);
-    case kStoreF32: return launch_step_t<float>(tab, grid, j, stats, st);
+    case kStoreF32:
+#if LBM_FP32_DMA
+        hipLaunchKernelGGL(step_kernel_f32, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
+        return hipGetLastError();
+#else
+        return launch_step_t<float>(tab, grid, j, stats, st);
+#endif
     default: return launch_step_t<_Float16>(tab, grid, j, stats, st);
     }
 }
@@ -673,7 +908,11 @@ const void *step_kernel_symbol(int storage)
 {
     switch (storage) {
     case kStoreF64: return reinterpret_cast<const void *>(&step_kernel<double>);
+#if LBM_FP32_DMA
+    case kStoreF32: return reinterpret_cast<const void *>(&step_kernel_f32);
+#else
     case kStoreF32: return reinterpret_cast<const void *>(&step_kernel<float>);
+#endif
     default: return reinterpret_cast<const void *>(&step_kernel<_Float16>);
     }
 }
