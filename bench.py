@@ -4,15 +4,24 @@
 Workload (default): periodic 128^3 compressible Taylor-Green vortex, Ma 0.5,
 Re 1600, gamma 1.4, FP64 storage and arithmetic (the plain FP64 GPU step).
 The same workload is also timed with FP32- and FP16-shifted storage and
-reported under "modes".  A step is one fused stream-and-collide launch over
+reported under "modes", and the serving mix (continuous batching against one
+solve at a time) under "serving".  A step is one fused stream-and-collide launch over
 all cells (f and g).  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode fp64|fp32s|fp16s]
-                  [--n 128] [--no-modes] [--no-cpu]
+                  [--n 128] [--no-modes] [--no-cpu] [--no-serving]
+                  [--serving-requests 40] [--serving-rate 3.0] [--serving-only]
+  python bench.py --copy-probe   (plain device copy of 1 GiB x 5, used to
+                                  calibrate the FETCH_SIZE / WRITE_SIZE counters)
+
+roofline.traffic is read from profiles/traffic.json (HBM bytes per launch from
+rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by the copy calibration) and is null
+unless that file was taken from the current kernel sources.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -77,6 +86,76 @@ def run_mode(mode, n, steps, warmup):
     }
 
 
+KERNEL_SOURCES = ["lbm_kernels.hip", "equilibrium.h", "d3q39.h", "slot.h"]
+
+
+def kernel_hash() -> str:
+    """Hash of the device sources, to tie counter data to the kernel it came from."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1910_13515_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(mode: str):
+    """HBM bytes per launch of the step kernel from the committed counter
+    summary, or None when it is missing or was taken from other sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash() or mode not in t.get("modes", {}):
+        return None
+    return t["modes"][mode]["hbm_bytes_per_launch"]
+
+
+def copy_probe(gib=1, reps=5):
+    """A plain device-to-device copy of known size (counter calibration)."""
+    import torch
+    n = gib * (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"copy_bytes_each_way": n * 4, "reps": reps, "GBps": 2 * n * 4 * reps / dt / 1e9}), flush=True)
+
+
+SERVING_MIX = dict(tube_cells=(200, 4000), box_cells=(64, 192), steps=(200, 2000), ratio=(2.0, 10.0),
+                   mach=(0.3, 1.5), reynolds=(1e3, 1e4))
+
+
+def serving_leg(count, rate, seed=2024, arena_gib=96, max_slots=64, graph_steps=32):
+    """The serving mix (seeded Poisson arrivals of tubes and boxes, FP32
+    shifted storage): continuous batching in the pool against the same trace
+    solved one at a time with the plain calls."""
+    import torch
+    from paper_1910_13515_amd import inputs, serve
+    trace = inputs.serving_trace(seed, count, rate, **SERVING_MIX)
+    pool = serve.Pool(arena_gib << 30, storage="fp32s", max_slots=max_slots, graph_steps=graph_steps)
+    # warm the graph and the admission path once (untimed)
+    warm = inputs.serving_trace(seed + 1, 2, 1e6, tube_cells=(200, 400), box_cells=(16, 16), steps=(40, 40))
+    serve.serve_batched(warm, pool, realtime=False)
+    _, batched = serve.serve_batched(trace, pool)
+    pool.close()
+    del pool
+    torch.cuda.empty_cache()
+    print(f"# serving batched: p50 {batched['p50_s']:.3f} s p99 {batched['p99_s']:.3f} s "
+          f"{batched['aggregate_glups']:.3f} GLUPS", file=sys.stderr, flush=True)
+    _, seq = serve.serve_sequential(trace, storage="fp32s")
+    print(f"# serving one-at-a-time: p50 {seq['p50_s']:.3f} s p99 {seq['p99_s']:.3f} s "
+          f"{seq['aggregate_glups']:.3f} GLUPS", file=sys.stderr, flush=True)
+    return {"trace": {"seed": seed, "requests": count, "rate_per_s": rate, "storage": "fp32s", **SERVING_MIX},
+            "pool": {"arena_gib": arena_gib, "max_slots": max_slots, "graph_steps": graph_steps},
+            "batched": batched, "one_at_a_time": seq}
+
+
 def cpu_baseline(seconds_target=15.0):
     """The FP64 oracle on the host cores: TGV 32^3 (same Ma, Re), a bounded
     number of steps.  Reported in GLUPS."""
@@ -108,6 +187,11 @@ def main():
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--no-modes", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=40)
+    ap.add_argument("--serving-rate", type=float, default=3.0)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the single-domain path is not sharded across GPUs "
@@ -116,8 +200,14 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe()
+        return
     from paper_1910_13515_amd import lbm
     lbm.load()
+    if args.serving_only:
+        print(json.dumps({"serving": serving_leg(args.serving_requests, args.serving_rate)}), flush=True)
+        return
 
     main_res = run_mode(args.mode, args.n, args.steps, args.warmup)
     print(f"# {args.mode}: {main_res['glups']:.3f} GLUPS, {main_res['ms_per_step']:.3f} ms/step", file=sys.stderr,
@@ -130,8 +220,12 @@ def main():
             r = run_mode(m, args.n, args.steps, args.warmup)
             print(f"# {m}: {r['glups']:.3f} GLUPS, {r['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
             modes[m] = r
+    serving = None if args.no_serving else serving_leg(args.serving_requests, args.serving_rate)
     cpu = None if args.no_cpu else cpu_baseline()
     roof = dict(main_res["roofline"])
+    roof["traffic"] = measured_traffic(args.mode)
+    for m, r in modes.items():
+        r["roofline"]["traffic"] = measured_traffic(m)
     out = {
         "metric": "GLUPS (D3Q39 f+g cell updates per second)",
         "value": main_res["glups"],
@@ -152,6 +246,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "modes": modes,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

@@ -165,6 +165,66 @@ int lbm_destroy(lbm_ctx *ctx);
  * call that had no context (ctx = NULL).  Never NULL. */
 const char *lbm_last_error(const lbm_ctx *ctx);
 
+/* ------------------------------------------------------------------------
+ * Serving pool: many independent solves resident in one device arena and
+ * advanced together.  Not a construct of the paper; it batches the step of
+ * Sec. 3 across solves.  Every active solve is one slot of a single slot
+ * table; one launch of the fused step kernel advances all of them (its
+ * persistent grid strides over the row blocks of every slot), and a captured
+ * HIP graph holds graph_steps such launches.  Solves may differ in grid,
+ * parameters and step count but share the storage mode.  A slot's arithmetic
+ * is exactly that of the same solve run alone with lbm_step().
+ * ------------------------------------------------------------------------ */
+typedef struct lbm_pool lbm_pool;
+
+typedef struct {
+    int32_t max_slots;         /* capacity of the slot table */
+    int32_t active;            /* admitted solves not yet released */
+    int32_t running;           /* active solves with steps left */
+    int32_t graph_steps;       /* steps per lbm_pool_run() */
+    int64_t arena_bytes;       /* caller's arena */
+    int64_t free_bytes;        /* total free bytes of the slot heap */
+    int64_t largest_free;      /* largest admissible footprint right now */
+} lbm_pool_info;
+
+/* Device bytes the pool itself needs besides its slots (slot table). */
+int64_t lbm_pool_overhead_bytes(int32_t max_slots);
+
+/* Creates a pool over a caller-owned device arena (256-byte aligned).  The
+ * slots' footprints (lbm_required_bytes) are carved from the arena beyond the
+ * pool overhead.  storage: lbm_storage shared by all slots.  graph_steps >= 1.
+ * hip_stream NULL: the pool creates its own stream.  Captures the graph. */
+int lbm_pool_create(int32_t storage, int32_t max_slots, int32_t graph_steps, void *dev_arena, int64_t arena_bytes,
+                    void *hip_stream, lbm_pool **out);
+
+/* Admits a solve of nsteps steps: sub-allocates its footprint (first fit),
+ * creates it in place (initial state written, as lbm_create) and returns its
+ * slot index.  LBM_E_NOMEM when no slot or no free range fits (nothing is
+ * changed); other errors as lbm_create. */
+int lbm_pool_admit(lbm_pool *pool, const lbm_params *params, int32_t nsteps, int32_t *slot_out);
+
+/* Advances every slot with steps left by min(graph_steps, steps left) steps in
+ * one graph launch and waits for it.  finished (nullable, max_slots entries)
+ * receives the slots that reached their step count in this call, *nfinished
+ * their number.  Returns LBM_OK (also when nothing was running). */
+int lbm_pool_run(lbm_pool *pool, int32_t *finished, int32_t *nfinished);
+
+/* Steps taken and steps still to run of a slot. */
+int lbm_pool_slot_progress(const lbm_pool *pool, int32_t slot, int64_t *steps_done, int64_t *steps_left);
+
+/* Moments of a slot, as lbm_moments(). */
+int lbm_pool_moments(lbm_pool *pool, int32_t slot, double *out_host, double *totals);
+
+/* Releases a slot and its arena range. */
+int lbm_pool_release(lbm_pool *pool, int32_t slot);
+
+int lbm_pool_get_info(const lbm_pool *pool, lbm_pool_info *info);
+
+/* Releases every slot, the graph and the pool (not the caller's arena). */
+int lbm_pool_destroy(lbm_pool *pool);
+
+const char *lbm_pool_last_error(const lbm_pool *pool);
+
 #ifdef __cplusplus
 }
 #endif

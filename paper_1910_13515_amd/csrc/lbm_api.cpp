@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -627,5 +628,334 @@ int lbm_destroy(lbm_ctx *c)
 }
 
 const char *lbm_last_error(const lbm_ctx *c) { return c ? c->err.c_str() : g_last_error.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Serving pool
+// ---------------------------------------------------------------------------
+namespace {
+
+struct PoolSlot {
+    bool used = false;
+    lbm_ctx *ctx = nullptr;
+    int64_t off = 0, bytes = 0;
+    int64_t steps_total = 0, steps_left = 0;
+};
+
+// first-fit allocator over [base, base + size) in 256-byte units
+struct RangeHeap {
+    std::map<int64_t, int64_t> free_;  // offset -> size
+    void init(int64_t base, int64_t size)
+    {
+        free_.clear();
+        if (size > 0) free_[base] = size;
+    }
+    int64_t alloc(int64_t bytes)
+    {
+        bytes = align_up(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const int64_t off = it->first, rest = it->second - bytes;
+                free_.erase(it);
+                if (rest > 0) free_[off + bytes] = rest;
+                return off;
+            }
+        }
+        return -1;
+    }
+    void release(int64_t off, int64_t bytes)
+    {
+        bytes = align_up(bytes);
+        auto it = free_.emplace(off, bytes).first;
+        auto next = std::next(it);
+        if (next != free_.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_.erase(next);
+        }
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    int64_t total() const
+    {
+        int64_t t = 0;
+        for (auto &kv : free_) t += kv.second;
+        return t;
+    }
+    int64_t largest() const
+    {
+        int64_t t = 0;
+        for (auto &kv : free_) t = std::max(t, kv.second);
+        return t;
+    }
+};
+
+}  // namespace
+
+struct lbm_pool {
+    int storage = 0, max_slots = 0, graph_steps = 1, grid = 8;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char *arena = nullptr;
+    int64_t arena_bytes = 0;
+    SlotTable *d_table = nullptr;
+    SlotTable *h_table = nullptr;  // pinned host copy
+    size_t table_bytes = 0;
+    RangeHeap heap;
+    std::vector<PoolSlot> slots;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::string err = "no error";
+};
+
+namespace {
+
+int pool_fail(lbm_pool *p, int code, const std::string &msg)
+{
+    if (p) p->err = msg;
+    else g_last_error = msg;
+    return code;
+}
+
+#define POOL_TRY(pool, expr)                                                                            \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess)                                                                           \
+            return pool_fail(pool, LBM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+void pool_free(lbm_pool *p)
+{
+    if (!p) return;
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    for (auto &s : p->slots)
+        if (s.used && s.ctx) lbm_destroy(s.ctx);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->h_table) (void)hipHostFree(p->h_table);
+    if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
+    delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t lbm_pool_overhead_bytes(int32_t max_slots)
+{
+    if (max_slots < 1 || max_slots > kMaxSlots) return fail(nullptr, LBM_E_INVAL, "max_slots out of range");
+    return align_up((int64_t)slot_table_bytes(max_slots));
+}
+
+int lbm_pool_create(int32_t storage, int32_t max_slots, int32_t graph_steps, void *dev_arena, int64_t arena_bytes,
+                    void *hip_stream, lbm_pool **out)
+{
+    if (!out) return fail(nullptr, LBM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (storage < LBM_STORE_FP64 || storage > LBM_STORE_FP16_SHIFTED) return fail(nullptr, LBM_E_INVAL, "unknown storage");
+    if (max_slots < 1 || max_slots > kMaxSlots) return fail(nullptr, LBM_E_INVAL, "max_slots out of range");
+    if (graph_steps < 1 || graph_steps > 4096) return fail(nullptr, LBM_E_INVAL, "graph_steps out of range");
+    if (!dev_arena || reinterpret_cast<uintptr_t>(dev_arena) % kAlign != 0)
+        return fail(nullptr, LBM_E_INVAL, "dev_arena must be a 256-byte aligned device pointer");
+    const int64_t head = lbm_pool_overhead_bytes(max_slots);
+    if (arena_bytes < head) return fail(nullptr, LBM_E_NOMEM, "arena smaller than the pool overhead");
+
+    lbm_pool *p = new (std::nothrow) lbm_pool();
+    if (!p) return fail(nullptr, LBM_E_NOMEM, "host allocation failed");
+    p->storage = storage;
+    p->max_slots = max_slots;
+    p->graph_steps = graph_steps;
+    p->arena = static_cast<char *>(dev_arena);
+    p->arena_bytes = arena_bytes;
+    p->table_bytes = slot_table_bytes(max_slots);
+    p->d_table = reinterpret_cast<SlotTable *>(p->arena);
+    p->heap.init(head, arena_bytes - head);
+    p->slots.resize(max_slots);
+    auto bail = [&](int code, const std::string &msg) {
+        g_last_error = msg;
+        pool_free(p);
+        return code;
+    };
+    if (hip_stream) {
+        p->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess)
+            return bail(LBM_E_DEVICE, "hipStreamCreateWithFlags failed");
+        p->own_stream = true;
+    }
+    if (hipHostMalloc(reinterpret_cast<void **>(&p->h_table), p->table_bytes, hipHostMallocDefault) != hipSuccess)
+        return bail(LBM_E_DEVICE, "hipHostMalloc failed");
+    std::memset(p->h_table, 0, p->table_bytes);
+    if (hipMemcpyAsync(p->d_table, p->h_table, p->table_bytes, hipMemcpyHostToDevice, p->stream) != hipSuccess ||
+        hipStreamSynchronize(p->stream) != hipSuccess)
+        return bail(LBM_E_DEVICE, "slot table upload failed");
+    {
+        int dev = 0, per_cu = 1;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+            return bail(LBM_E_DEVICE, "no HIP device");
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            return bail(LBM_E_DEVICE, std::string("library built for gfx950, device is ") + prop.gcnArchName);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step_kernel_symbol(storage), kBlockThreads, 0) !=
+            hipSuccess)
+            return bail(LBM_E_DEVICE, "occupancy query failed");
+        int grid = std::max(1, per_cu) * prop.multiProcessorCount;
+        grid = std::min(grid, kMaxGrid);
+        p->grid = std::max(8, grid / 8 * 8);
+    }
+    // capture graph_steps launches of the batched step; the slot table (read
+    // by the kernel at run time) decides which slots each launch advances
+    if (hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return bail(LBM_E_DEVICE, "hipStreamBeginCapture failed");
+    for (int j = 0; j < graph_steps; ++j) {
+        if (launch_step(storage, p->d_table, p->grid, j, nullptr, p->stream) != hipSuccess) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(p->stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            return bail(LBM_E_DEVICE, "kernel launch during capture failed");
+        }
+    }
+    if (hipStreamEndCapture(p->stream, &p->graph) != hipSuccess) return bail(LBM_E_DEVICE, "hipStreamEndCapture failed");
+    if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
+        return bail(LBM_E_DEVICE, "hipGraphInstantiate failed");
+    *out = p;
+    return LBM_OK;
+}
+
+int lbm_pool_admit(lbm_pool *p, const lbm_params *params, int32_t nsteps, int32_t *slot_out)
+{
+    if (!p) return fail(nullptr, LBM_E_INVAL, "pool is NULL");
+    if (!params || !slot_out || nsteps < 0) return pool_fail(p, LBM_E_INVAL, "invalid argument");
+    if (params->storage != p->storage) return pool_fail(p, LBM_E_INVAL, "storage differs from the pool's");
+    const int64_t need = lbm_required_bytes(params);
+    if (need < 0) return pool_fail(p, (int)need, lbm_last_error(nullptr));
+    int slot = -1;
+    for (int i = 0; i < p->max_slots; ++i)
+        if (!p->slots[i].used) {
+            slot = i;
+            break;
+        }
+    if (slot < 0) return pool_fail(p, LBM_E_NOMEM, "no free slot");
+    const int64_t off = p->heap.alloc(need);
+    if (off < 0) return pool_fail(p, LBM_E_NOMEM, "no free range of " + std::to_string(need) + " bytes");
+    lbm_ctx *ctx = nullptr;
+    const int rc = lbm_create(params, p->arena + off, need, p->stream, &ctx);
+    if (rc != LBM_OK) {
+        p->heap.release(off, need);
+        return pool_fail(p, rc, lbm_last_error(nullptr));
+    }
+    PoolSlot &s = p->slots[slot];
+    s.used = true;
+    s.ctx = ctx;
+    s.off = off;
+    s.bytes = need;
+    s.steps_total = nsteps;
+    s.steps_left = nsteps;
+    *slot_out = slot;
+    return LBM_OK;
+}
+
+int lbm_pool_run(lbm_pool *p, int32_t *finished, int32_t *nfinished)
+{
+    if (!p) return fail(nullptr, LBM_E_INVAL, "pool is NULL");
+    if (nfinished) *nfinished = 0;
+    SlotTable *t = p->h_table;
+    int n = 0, blocks = 0;
+    std::vector<int> order;
+    for (int i = 0; i < p->max_slots; ++i) {
+        const PoolSlot &s = p->slots[i];
+        if (!s.used || s.steps_left <= 0) continue;
+        SlotDesc d = s.ctx->desc;
+        d.parity0 = (int32_t)(s.ctx->steps & 1);
+        d.steps_todo = (int32_t)std::min<int64_t>(p->graph_steps, s.steps_left);
+        d.stats = nullptr;
+        t->slot[n] = d;
+        t->block_start[n] = blocks;
+        blocks += d.blocks;
+        order.push_back(i);
+        ++n;
+    }
+    if (n == 0) return LBM_OK;
+    t->nslots = n;
+    t->block_start[n] = blocks;
+    t->total_blocks = blocks;
+    POOL_TRY(p, hipMemcpyAsync(p->d_table, t, slot_table_bytes(n), hipMemcpyHostToDevice, p->stream));
+    POOL_TRY(p, hipGraphLaunch(p->exec, p->stream));
+    POOL_TRY(p, hipStreamSynchronize(p->stream));
+    int nf = 0;
+    for (int k = 0; k < n; ++k) {
+        PoolSlot &s = p->slots[order[k]];
+        const int64_t adv = std::min<int64_t>(p->graph_steps, s.steps_left);
+        s.ctx->steps += adv;
+        s.steps_left -= adv;
+        if (s.steps_left == 0) {
+            if (finished) finished[nf] = order[k];
+            ++nf;
+        }
+    }
+    if (nfinished) *nfinished = nf;
+    return LBM_OK;
+}
+
+int lbm_pool_slot_progress(const lbm_pool *p, int32_t slot, int64_t *steps_done, int64_t *steps_left)
+{
+    if (!p || slot < 0 || slot >= p->max_slots || !p->slots[slot].used)
+        return fail(nullptr, LBM_E_INVAL, "invalid pool or slot");
+    if (steps_done) *steps_done = p->slots[slot].steps_total - p->slots[slot].steps_left;
+    if (steps_left) *steps_left = p->slots[slot].steps_left;
+    return LBM_OK;
+}
+
+int lbm_pool_moments(lbm_pool *p, int32_t slot, double *out_host, double *totals)
+{
+    if (!p || slot < 0 || slot >= p->max_slots || !p->slots[slot].used)
+        return fail(nullptr, LBM_E_INVAL, "invalid pool or slot");
+    const int rc = lbm_moments(p->slots[slot].ctx, out_host, totals);
+    if (rc != LBM_OK) p->err = lbm_last_error(p->slots[slot].ctx);
+    return rc;
+}
+
+int lbm_pool_release(lbm_pool *p, int32_t slot)
+{
+    if (!p || slot < 0 || slot >= p->max_slots || !p->slots[slot].used)
+        return fail(nullptr, LBM_E_INVAL, "invalid pool or slot");
+    PoolSlot &s = p->slots[slot];
+    const int rc = lbm_destroy(s.ctx);
+    p->heap.release(s.off, s.bytes);
+    s = PoolSlot();
+    if (rc != LBM_OK) return pool_fail(p, rc, lbm_last_error(nullptr));
+    return LBM_OK;
+}
+
+int lbm_pool_get_info(const lbm_pool *p, lbm_pool_info *info)
+{
+    if (!p || !info) return fail(nullptr, LBM_E_INVAL, "pool or info is NULL");
+    info->max_slots = p->max_slots;
+    info->active = 0;
+    info->running = 0;
+    for (auto &s : p->slots) {
+        info->active += s.used;
+        info->running += s.used && s.steps_left > 0;
+    }
+    info->graph_steps = p->graph_steps;
+    info->arena_bytes = p->arena_bytes;
+    info->free_bytes = p->heap.total();
+    info->largest_free = p->heap.largest();
+    return LBM_OK;
+}
+
+int lbm_pool_destroy(lbm_pool *p)
+{
+    if (!p) return fail(nullptr, LBM_E_INVAL, "pool is NULL");
+    pool_free(p);
+    return LBM_OK;
+}
+
+const char *lbm_pool_last_error(const lbm_pool *p) { return p ? p->err.c_str() : g_last_error.c_str(); }
 
 }  // extern "C"

@@ -127,17 +127,17 @@ __device__ __forceinline__ C load_pop(const S *buf, int64_t n, int pop, int64_t 
 }
 
 // wave-level integer reductions (64 lanes)
-__device__ __forceinline__ int64_t wave_sum(int64_t v)
+__device__ __forceinline__ int32_t wave_sum(int32_t v)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
-__device__ __forceinline__ int64_t wave_max(int64_t v)
+__device__ __forceinline__ int32_t wave_max(int32_t v)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
-        const int64_t w = __shfl_xor(v, o, 64);
+        const int32_t w = __shfl_xor(v, o, 64);
         v = w > v ? w : v;
     }
     return v;
@@ -254,7 +254,7 @@ using VelSeq = std::make_integer_sequence<int, kQ>;
 template <class S>
 __device__ __forceinline__ void update_cell(const SlotDesc &d, const S *src, S *dst, int x, int y, int z,
                                             uint32_t cell, const Park<typename StoreTraits<S>::C> &pk,
-                                            int64_t (&acc)[kStatWords])
+                                            int32_t (&acc)[kStatWords])
 {
     using C = typename StoreTraits<S>::C;
     const uint64_t links = d.has_links ? d.links[cell] : 0ull;
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(kBlockThreads, StoreTraits<S>::kWavesPerSimd) void 
     using C = typename StoreTraits<S>::C;
     __shared__ C park[2 * kQ * kBlockThreads];
     const Park<C> pk{park + threadIdx.x};
-    int64_t acc[kStatWords] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int32_t acc[kStatWords] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int total = tab->total_blocks;
     const int xcd = blockIdx.x & 7;
     const int per_xcd = gridDim.x >> 3;
@@ -396,21 +396,23 @@ __global__ __launch_bounds__(kBlockThreads, StoreTraits<S>::kWavesPerSimd) void 
         const int y = row % d.ny;
         const int z = row / d.ny;
         const int x = segx * kSegment + lane;
-        int64_t it_cell = 0;
+        int32_t it_cell = 0;
         if (x < d.nx && is_fluid_coord(d, x, y, z)) {
             const int par = (d.parity0 + j) & 1;
             const S *src = static_cast<const S *>(d.buf[par]);
             S *dst = static_cast<S *>(d.buf[par ^ 1]);
             const uint32_t cell = (uint32_t)x + (uint32_t)d.nx * ((uint32_t)y + (uint32_t)d.ny * (uint32_t)z);
-            const int64_t it_before = acc[0];
+            const int32_t it_before = acc[0];
             update_cell<S>(d, src, dst, x, y, z, cell, pk, acc);
             it_cell = acc[0] - it_before;
         }
         // per-wave cost: the wave runs as many updates as its slowest cell
         // (all 64 lanes are converged here)
-        const int64_t wmax = wave_max(it_cell);
-        acc[8] += lane == 0 ? wmax : 0;
-        acc[9] += lane == 0 ? 1 : 0;
+        if (stats) {
+            const int32_t wmax = wave_max(it_cell);
+            acc[8] += lane == 0 ? wmax : 0;
+            acc[9] += lane == 0 ? 1 : 0;
+        }
     }
     if (stats) {
         int64_t red[kStatWords];
@@ -491,7 +493,7 @@ __device__ __forceinline__ void gather(const SlotDesc &d, gcbyte *srcb, int x, i
 // moments, Newton, sensor and relaxation of one fluid cell whose gathered
 // values sit in LDS; the results replace them
 __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const Park<float> &pk,
-                                        int64_t (&acc)[kStatWords])
+                                        int32_t (&acc)[kStatWords])
 {
     using C = float;
     using S = float;
@@ -571,7 +573,7 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f32(const SlotTa
 {
     __shared__ float park[2 * kQ * kBlockThreads];
     const Park<float> pk{park + threadIdx.x};
-    int64_t acc[kStatWords] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int32_t acc[kStatWords] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int total = tab->total_blocks;
     const int xcd = blockIdx.x & 7;
     const int per_xcd = gridDim.x >> 3;
@@ -604,15 +606,17 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f32(const SlotTa
         if (links >> 63) fluid = false;  // solid cells pass through unchanged
         if (in_grid) f32::gather(d, srcb, x, y, z, cell, links, !fluid, rows);
         f32::wait_vmem();
-        int64_t it_cell = 0;
+        int32_t it_cell = 0;
         if (fluid) {
-            const int64_t before = acc[0];
+            const int32_t before = acc[0];
             f32::collide(d, cell, pk, acc);
             it_cell = acc[0] - before;
         }
-        const int64_t wmax = wave_max(it_cell);
-        acc[8] += lane == 0 ? wmax : 0;
-        acc[9] += lane == 0 ? 1 : 0;
+        if (stats) {
+            const int32_t wmax = wave_max(it_cell);
+            acc[8] += lane == 0 ? wmax : 0;
+            acc[9] += lane == 0 ? 1 : 0;
+        }
         // store the wave's rows
         const uint64_t nS64 = (uint64_t)d.n * 4;
         const float *col = park + wave * kSegment;

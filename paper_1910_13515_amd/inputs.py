@@ -150,6 +150,7 @@ class Request:
     mach: float = 0.0
     reynolds: float = 0.0
     tau: float = 0.0
+    T_ref: float = 0.5      # reference temperature (relaxation time, shift weights)
     rho: np.ndarray = field(default=None, repr=False)
     u: np.ndarray = field(default=None, repr=False)
     T: np.ndarray = field(default=None, repr=False)
@@ -157,12 +158,20 @@ class Request:
 
 def serving_trace(seed: int, count: int, rate: float, T_ref: float = 0.5, gamma: float = 1.4,
                   tube_cells=(200, 4000), box_cells=(64, 192), steps=(200, 2000), ratio=(2.0, 10.0),
-                  mach=(0.3, 1.5), reynolds=(1e3, 1e4), with_fields: bool = True):
+                  mach=(0.3, 1.5), reynolds=(1e3, 1e4), with_fields: bool = True, tube_T_hot: float = 0.8,
+                  tube_T_ratio_max: float = 3.2):
     """Poisson arrivals (exponential gaps of mean 1/rate) of independent
     solves, half 1-D Riemann tubes (x periodic, left state denser and hotter
     by the drawn ratios) and half periodic 3-D boxes with a random-phase
-    solenoidal velocity.  Tube temperatures are scaled so the hot side sits
-    at T_ref; box velocities are Ma sqrt(gamma T_ref) at their maximum.
+    solenoidal velocity.  Box velocities are Ma sqrt(gamma T_ref) at their
+    maximum, at uniform T_ref.
+
+    Tubes stay inside the temperature window where the D3Q39 equilibrium
+    exists along the whole run: the density ratio is drawn from ``ratio``, the
+    pressure ratio from ``ratio`` limited to [density ratio, density ratio *
+    tube_T_ratio_max] (the dense side is never the colder one, and the two
+    temperatures differ by at most tube_T_ratio_max), and the hot side sits at
+    tube_T_hot, which is also the tube's reference temperature.
     Relaxation times are left to the solver (``reynolds`` and the reference
     length n/2pi of a box or n/8 of a tube)."""
     rng = np.random.default_rng(seed)
@@ -174,20 +183,20 @@ def serving_trace(seed: int, count: int, rate: float, T_ref: float = 0.5, gamma:
         if rng.uniform() < 0.5:
             nx = int(rng.integers(tube_cells[0], tube_cells[1] + 1))
             rr = rng.uniform(*ratio)
-            pr = rng.uniform(*ratio)
+            pr = rng.uniform(max(rr, ratio[0]), min(ratio[1], rr * tube_T_ratio_max))
             re = float(np.exp(rng.uniform(np.log(reynolds[0]), np.log(reynolds[1]))))
-            req = Request(rid, t, "tube", (nx, 1, 1), nsteps, gamma=gamma, mach=0.0, reynolds=re)
+            req = Request(rid, t, "tube", (nx, 1, 1), nsteps, gamma=gamma, mach=0.0, reynolds=re,
+                          T_ref=tube_T_hot)
             if with_fields:
                 # left state (rho, p) = (rr, pr), right (1, 1); T = s p / rho with the
-                # hotter side at T_ref
-                tl, tr = pr / rr, 1.0
-                s = T_ref / max(tl, tr)
+                # left (hot) side at tube_T_hot
+                s = tube_T_hot * rr / pr
                 req.rho, req.u, req.T = sod_fields(nx, 1, 1, rho_l=rr, p_l=pr, rho_r=1.0, p_r=1.0, temp_scale=s)
         else:
             nb = int(rng.integers(box_cells[0], box_cells[1] + 1))
             ma = float(rng.uniform(*mach))
             re = float(np.exp(rng.uniform(np.log(reynolds[0]), np.log(reynolds[1]))))
-            req = Request(rid, t, "box", (nb, nb, nb), nsteps, gamma=gamma, mach=ma, reynolds=re)
+            req = Request(rid, t, "box", (nb, nb, nb), nsteps, gamma=gamma, mach=ma, reynolds=re, T_ref=T_ref)
             if with_fields:
                 umax = ma * math.sqrt(gamma * T_ref)
                 u = solenoidal_random_velocity(nb, int(rng.integers(1 << 31)), umax)

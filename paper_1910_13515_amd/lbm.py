@@ -36,7 +36,9 @@ LBM_FACE_EQUILIBRIUM = 1
 LBM_FACE_NEUMANN = 2
 
 EXPORTED = ["lbm_version", "lbm_velocities", "lbm_required_bytes", "lbm_create", "lbm_step", "lbm_moments",
-            "lbm_get_state", "lbm_set_state", "lbm_get_info", "lbm_destroy", "lbm_last_error"]
+            "lbm_get_state", "lbm_set_state", "lbm_get_info", "lbm_destroy", "lbm_last_error",
+            "lbm_pool_overhead_bytes", "lbm_pool_create", "lbm_pool_admit", "lbm_pool_run", "lbm_pool_slot_progress",
+            "lbm_pool_moments", "lbm_pool_release", "lbm_pool_get_info", "lbm_pool_destroy", "lbm_pool_last_error"]
 
 
 class lbm_params(ctypes.Structure):
@@ -65,6 +67,14 @@ class lbm_info(ctypes.Structure):
         ("tau", ctypes.c_double), ("u_ref", ctypes.c_double * 3), ("shear_response", ctypes.c_double),
         ("delta", ctypes.c_double), ("cells", ctypes.c_int64), ("fluid_cells", ctypes.c_int64),
         ("steps_done", ctypes.c_int64), ("arena_bytes_used", ctypes.c_int64),
+    ]
+
+
+class lbm_pool_info(ctypes.Structure):
+    _fields_ = [
+        ("max_slots", ctypes.c_int32), ("active", ctypes.c_int32), ("running", ctypes.c_int32),
+        ("graph_steps", ctypes.c_int32), ("arena_bytes", ctypes.c_int64), ("free_bytes", ctypes.c_int64),
+        ("largest_free", ctypes.c_int64),
     ]
 
 
@@ -101,6 +111,26 @@ def load() -> ctypes.CDLL:
     L.lbm_destroy.argtypes = [vp]
     L.lbm_last_error.restype = ctypes.c_char_p
     L.lbm_last_error.argtypes = [vp]
+    L.lbm_pool_overhead_bytes.restype = i64
+    L.lbm_pool_overhead_bytes.argtypes = [i32]
+    L.lbm_pool_create.restype = ctypes.c_int
+    L.lbm_pool_create.argtypes = [i32, i32, i32, vp, i64, vp, ctypes.POINTER(vp)]
+    L.lbm_pool_admit.restype = ctypes.c_int
+    L.lbm_pool_admit.argtypes = [vp, ctypes.POINTER(lbm_params), i32, ctypes.POINTER(i32)]
+    L.lbm_pool_run.restype = ctypes.c_int
+    L.lbm_pool_run.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.lbm_pool_slot_progress.restype = ctypes.c_int
+    L.lbm_pool_slot_progress.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.lbm_pool_moments.restype = ctypes.c_int
+    L.lbm_pool_moments.argtypes = [vp, i32, vp, vp]
+    L.lbm_pool_release.restype = ctypes.c_int
+    L.lbm_pool_release.argtypes = [vp, i32]
+    L.lbm_pool_get_info.restype = ctypes.c_int
+    L.lbm_pool_get_info.argtypes = [vp, ctypes.POINTER(lbm_pool_info)]
+    L.lbm_pool_destroy.restype = ctypes.c_int
+    L.lbm_pool_destroy.argtypes = [vp]
+    L.lbm_pool_last_error.restype = ctypes.c_char_p
+    L.lbm_pool_last_error.argtypes = [vp]
     _lib = L
     return L
 
@@ -243,6 +273,24 @@ class Solver:
         aligned = (base + 255) // 256 * 256
         self.ctx = lbm_create(self.params, aligned, self.bytes, self.stream.cuda_stream)
         self._keep = []  # host inputs are copied during create
+
+    @classmethod
+    def from_params(cls, params: lbm_params, stream=None):
+        """A solve from ready lbm_params (host inputs it points to must stay
+        alive for this call only: the library copies them during create)."""
+        import torch
+        load()
+        s = cls.__new__(cls)
+        s.shape = (int(params.nx), int(params.ny), int(params.nz))
+        s.n = s.shape[0] * s.shape[1] * s.shape[2]
+        s.params = params
+        s._keep = []
+        s.bytes = lbm_required_bytes(params)
+        s.stream = stream if stream is not None else torch.cuda.current_stream()
+        s.arena = torch.empty(s.bytes + 256, dtype=torch.uint8, device="cuda")
+        aligned = (s.arena.data_ptr() + 255) // 256 * 256
+        s.ctx = lbm_create(params, aligned, s.bytes, s.stream.cuda_stream)
+        return s
 
     def step(self, nsteps=1, stats=False):
         st, code = lbm_step(self.ctx, nsteps, with_stats=stats)

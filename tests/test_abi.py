@@ -81,3 +81,27 @@ def test_null_arguments_are_rejected(L):
     assert L.lbm_step(None, 1, None) == lbm.LBM_E_INVAL
     assert L.lbm_moments(None, None, None) == lbm.LBM_E_INVAL
     assert L.lbm_destroy(None) == lbm.LBM_E_INVAL
+
+
+def test_pool_arguments_validated_without_device(L):
+    assert L.lbm_pool_overhead_bytes(0) == lbm.LBM_E_INVAL
+    head = L.lbm_pool_overhead_bytes(8)
+    assert head > 0 and head % 256 == 0
+    pool = ctypes.c_void_p()
+    ok = ctypes.c_void_p(1 << 20)  # aligned, never dereferenced: every call below fails first
+    assert L.lbm_pool_create(1, 8, 4, ok, 1 << 30, None, None) == lbm.LBM_E_INVAL
+    assert L.lbm_pool_create(7, 8, 4, ok, 1 << 30, None, ctypes.byref(pool)) == lbm.LBM_E_INVAL
+    assert L.lbm_pool_create(1, 0, 4, ok, 1 << 30, None, ctypes.byref(pool)) == lbm.LBM_E_INVAL
+    assert L.lbm_pool_create(1, 8, 0, ok, 1 << 30, None, ctypes.byref(pool)) == lbm.LBM_E_INVAL
+    assert L.lbm_pool_create(1, 8, 4, ctypes.c_void_p((1 << 20) + 8), 1 << 30, None,
+                             ctypes.byref(pool)) == lbm.LBM_E_INVAL
+    assert L.lbm_pool_create(1, 8, 4, ok, head - 256, None, ctypes.byref(pool)) == lbm.LBM_E_NOMEM
+    assert not pool.value
+    slot = ctypes.c_int32()
+    p = lbm.make_params((16, 8, 1), tau=0.6)
+    assert L.lbm_pool_admit(None, ctypes.byref(p), 1, ctypes.byref(slot)) == lbm.LBM_E_INVAL
+    assert L.lbm_pool_run(None, None, None) == lbm.LBM_E_INVAL
+    assert L.lbm_pool_moments(None, 0, None, None) == lbm.LBM_E_INVAL
+    assert L.lbm_pool_release(None, 0) == lbm.LBM_E_INVAL
+    assert L.lbm_pool_destroy(None) == lbm.LBM_E_INVAL
+    assert L.lbm_pool_last_error(None)

@@ -1,0 +1,104 @@
+"""Serving pool on the GPU: every solve of a mixed batch gives exactly the
+result it gives alone, admission is by HBM footprint, and the continuous
+batching loop retires every request of a trace."""
+import numpy as np
+import pytest
+
+from paper_1910_13515_amd import inputs, lbm
+
+pytestmark = pytest.mark.gpu
+
+
+def _trace(seed, count, **kw):
+    kw.setdefault("tube_cells", (90, 260))
+    kw.setdefault("box_cells", (6, 14))
+    kw.setdefault("steps", (5, 37))
+    kw.setdefault("mach", (0.2, 0.8))
+    return inputs.serving_trace(seed, count, rate=1e6, **kw)
+
+
+def _first(kind, seed=3, **kw):
+    return next(r for r in _trace(seed, 16, **kw) if r.kind == kind)
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32s", "fp16s"])
+def test_mix_equals_alone_bitwise(storage):
+    from paper_1910_13515_amd import serve
+    trace = _trace(11, 9)
+    fps = [serve.footprint(r, storage) for r in trace]
+    # room for about half of them at once: admission waits, slots are reused
+    room = max(sum(fps) // 2, max(fps)) + (1 << 20)
+    pool = serve.Pool(lbm.load().lbm_pool_overhead_bytes(4) + room, storage=storage, max_slots=4, graph_steps=8)
+    outs, summary = serve.serve_batched(trace, pool, keep_fields=True, realtime=False)
+    assert summary["requests"] == len(trace)
+    inf = pool.info()
+    assert inf.active == 0 and inf.free_bytes == inf.arena_bytes - lbm.load().lbm_pool_overhead_bytes(4)
+    pool.close()
+    for r, o in zip(trace, outs):
+        fields, tot = serve.solve_alone(r, storage)
+        assert np.array_equal(o.fields, fields), (r.rid, r.kind, r.shape, r.steps)
+        assert np.array_equal(o.totals, tot), r.rid
+
+
+def test_admission_by_footprint_and_release():
+    from paper_1910_13515_amd import serve
+    L = lbm.load()
+    req = _first("box", box_cells=(12, 12), steps=(10, 10))
+    fp = serve.footprint(req, "fp32s")
+    head = L.lbm_pool_overhead_bytes(8)
+    pool = serve.Pool(head + 2 * fp + 4096, storage="fp32s", max_slots=8, graph_steps=4)
+    a = pool.admit(req)
+    b = pool.admit(req)
+    assert a is not None and b is not None and a != b
+    assert pool.admit(req) is None  # no free range: refused, nothing changed
+    inf = pool.info()
+    assert inf.active == 2 and inf.running == 2 and inf.largest_free < fp
+    # storage mismatch is an argument error, not a refusal
+    p, _ = serve.request_params(req, "fp64")
+    import ctypes
+    slot = ctypes.c_int32()
+    assert L.lbm_pool_admit(pool.h, ctypes.byref(p), 1, ctypes.byref(slot)) == lbm.LBM_E_INVAL
+    done = []
+    for _ in range(3):
+        done += pool.run()
+    assert sorted(done) == sorted([a, b])
+    assert pool.run() == []  # nothing running: a no-op
+    pool.release(a)
+    c = pool.admit(req)
+    assert c is not None
+    assert pool.info().active == 2
+    pool.close()
+
+
+def test_zero_step_request_keeps_initial_state():
+    from paper_1910_13515_amd import serve
+    req = _first("box", seed=5, box_cells=(8, 8), steps=(1, 1))
+    req.steps = 0
+    pool = serve.Pool(64 << 20, storage="fp64", max_slots=2, graph_steps=4)
+    slot = pool.admit(req)
+    assert pool.run() == []
+    f0, t0 = pool.moments(slot, int(np.prod(req.shape)), fields=True)
+    p, keep = serve.request_params(req, "fp64")
+    s = lbm.Solver.from_params(p)
+    f1, t1 = s.moments()
+    assert np.array_equal(f0, f1) and np.array_equal(t0, t1)
+    s.close()
+    pool.release(slot)
+    # the serving loop retires a zero-step request at admission
+    outs, summary = serve.serve_batched([req], pool, realtime=False)
+    assert summary["requests"] == 1 and np.array_equal(outs[0].totals, t1)
+    pool.close()
+
+
+def test_realtime_trace_latencies():
+    from paper_1910_13515_amd import serve
+    trace = inputs.serving_trace(21, 12, rate=200.0, tube_cells=(90, 200), box_cells=(8, 16), steps=(20, 60),
+                                 mach=(0.2, 0.6))
+    pool = serve.Pool(256 << 20, storage="fp32s", max_slots=16, graph_steps=16)
+    outs, summary = serve.serve_batched(trace, pool)
+    pool.close()
+    assert summary["requests"] == 12
+    assert 0.0 < summary["p50_s"] <= summary["p99_s"] <= summary["max_s"]
+    for o in outs:
+        assert o.arrival <= o.admitted <= o.done
+        assert np.all(np.isfinite(o.totals))
