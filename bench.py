@@ -131,14 +131,14 @@ SERVING_MIX = dict(tube_cells=(200, 4000), box_cells=(64, 192), steps=(200, 2000
                    mach=(0.3, 1.5), reynolds=(1e3, 1e4))
 
 
-def serving_leg(count, rate, seed=2024, arena_gib=96, max_slots=64, graph_steps=32):
+def serving_leg(count, rate, seed=2024, arena_gib=96, max_slots=64, graph_steps=32, sched="srpt", sequential=True):
     """The serving mix (seeded Poisson arrivals of tubes and boxes, FP32
     shifted storage): continuous batching in the pool against the same trace
     solved one at a time with the plain calls."""
     import torch
     from paper_1910_13515_amd import inputs, serve
     trace = inputs.serving_trace(seed, count, rate, **SERVING_MIX)
-    pool = serve.Pool(arena_gib << 30, storage="fp32s", max_slots=max_slots, graph_steps=graph_steps)
+    pool = serve.Pool(arena_gib << 30, storage="fp32s", max_slots=max_slots, graph_steps=graph_steps, sched=sched)
     # warm the graph and the admission path once (untimed)
     warm = inputs.serving_trace(seed + 1, 2, 1e6, tube_cells=(200, 400), box_cells=(16, 16), steps=(40, 40))
     serve.serve_batched(warm, pool, realtime=False)
@@ -146,14 +146,17 @@ def serving_leg(count, rate, seed=2024, arena_gib=96, max_slots=64, graph_steps=
     pool.close()
     del pool
     torch.cuda.empty_cache()
-    print(f"# serving batched: p50 {batched['p50_s']:.3f} s p99 {batched['p99_s']:.3f} s "
+    print(f"# serving batched ({sched}): p50 {batched['p50_s']:.3f} s p99 {batched['p99_s']:.3f} s "
           f"{batched['aggregate_glups']:.3f} GLUPS", file=sys.stderr, flush=True)
-    _, seq = serve.serve_sequential(trace, storage="fp32s")
-    print(f"# serving one-at-a-time: p50 {seq['p50_s']:.3f} s p99 {seq['p99_s']:.3f} s "
-          f"{seq['aggregate_glups']:.3f} GLUPS", file=sys.stderr, flush=True)
-    return {"trace": {"seed": seed, "requests": count, "rate_per_s": rate, "storage": "fp32s", **SERVING_MIX},
-            "pool": {"arena_gib": arena_gib, "max_slots": max_slots, "graph_steps": graph_steps},
-            "batched": batched, "one_at_a_time": seq}
+    out = {"trace": {"seed": seed, "requests": count, "rate_per_s": rate, "storage": "fp32s", **SERVING_MIX},
+           "pool": {"arena_gib": arena_gib, "max_slots": max_slots, "graph_steps": graph_steps, "sched": sched},
+           "batched": batched}
+    if sequential:
+        _, seq = serve.serve_sequential(trace, storage="fp32s")
+        print(f"# serving one-at-a-time: p50 {seq['p50_s']:.3f} s p99 {seq['p99_s']:.3f} s "
+              f"{seq['aggregate_glups']:.3f} GLUPS", file=sys.stderr, flush=True)
+        out["one_at_a_time"] = seq
+    return out
 
 
 def cpu_baseline(seconds_target=15.0):

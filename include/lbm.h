@@ -168,20 +168,38 @@ const char *lbm_last_error(const lbm_ctx *ctx);
 /* ------------------------------------------------------------------------
  * Serving pool: many independent solves resident in one device arena and
  * advanced together.  Not a construct of the paper; it batches the step of
- * Sec. 3 across solves.  Every active solve is one slot of a single slot
- * table; one launch of the fused step kernel advances all of them (its
- * persistent grid strides over the row blocks of every slot), and a captured
- * HIP graph holds graph_steps such launches.  Solves may differ in grid,
- * parameters and step count but share the storage mode.  A slot's arithmetic
- * is exactly that of the same solve run alone with lbm_step().
+ * Sec. 3 across solves.  Every solve is one slot; a round advances the slots
+ * the scheduling policy picks by one launch of a captured HIP graph of
+ * graph_steps launches of the fused step kernel, whose persistent grid strides
+ * over the row blocks of every picked slot (a slot table in device memory
+ * tells each launch which slots to advance and from which buffer).  Solves may
+ * differ in grid, parameters and step count but share the storage mode.  A
+ * slot's arithmetic is exactly that of the same solve run alone with
+ * lbm_step(), whatever the other slots are.
+ *
+ * Streams: rounds run on the pool's stream; admission (lbm_create of the
+ * slot), moments and release run on a second stream the pool owns, so they
+ * overlap a round in flight.  A round waits for the last admission.
+ * One host thread drives a pool; calls on one pool must not overlap.
  * ------------------------------------------------------------------------ */
 typedef struct lbm_pool lbm_pool;
+
+typedef enum {
+    LBM_SCHED_ALL = 0,   /* every slot with steps left runs in every round */
+    LBM_SCHED_SRPT = 1   /* slots by least remaining work (fluid cells x steps
+                            left); the first always, further ones while the
+                            cells per step stay within max(fill_cells, cells of
+                            the first); the rest wait for a later round */
+} lbm_sched;
 
 typedef struct {
     int32_t max_slots;         /* capacity of the slot table */
     int32_t active;            /* admitted solves not yet released */
     int32_t running;           /* active solves with steps left */
-    int32_t graph_steps;       /* steps per lbm_pool_run() */
+    int32_t graph_steps;       /* steps per round */
+    int32_t sched;             /* lbm_sched */
+    int32_t in_flight;         /* 1 between lbm_pool_launch and lbm_pool_wait */
+    int64_t fill_cells;        /* SRPT cells-per-step bound in effect */
     int64_t arena_bytes;       /* caller's arena */
     int64_t free_bytes;        /* total free bytes of the slot heap */
     int64_t largest_free;      /* largest admissible footprint right now */
@@ -192,37 +210,55 @@ int64_t lbm_pool_overhead_bytes(int32_t max_slots);
 
 /* Creates a pool over a caller-owned device arena (256-byte aligned).  The
  * slots' footprints (lbm_required_bytes) are carved from the arena beyond the
- * pool overhead.  storage: lbm_storage shared by all slots.  graph_steps >= 1.
- * hip_stream NULL: the pool creates its own stream.  Captures the graph. */
-int lbm_pool_create(int32_t storage, int32_t max_slots, int32_t graph_steps, void *dev_arena, int64_t arena_bytes,
-                    void *hip_stream, lbm_pool **out);
+ * pool overhead.  storage: lbm_storage shared by all slots.  graph_steps in
+ * [1, 4096].  sched: lbm_sched.  fill_cells: SRPT bound, 0 = four row blocks
+ * per resident workgroup of the persistent grid.  hip_stream NULL: the pool
+ * creates its own stream.  Captures the graph.  LBM_E_NOMEM when the arena
+ * cannot hold the overhead. */
+int lbm_pool_create(int32_t storage, int32_t max_slots, int32_t graph_steps, int32_t sched, int64_t fill_cells,
+                    void *dev_arena, int64_t arena_bytes, void *hip_stream, lbm_pool **out);
 
 /* Admits a solve of nsteps steps: sub-allocates its footprint (first fit),
- * creates it in place (initial state written, as lbm_create) and returns its
- * slot index.  LBM_E_NOMEM when no slot or no free range fits (nothing is
- * changed); other errors as lbm_create. */
+ * creates it in place on the admission stream (initial state written, as
+ * lbm_create) and returns its slot index.  Allowed while a round is in flight.
+ * LBM_E_NOMEM when no slot or no free range fits (nothing is changed); other
+ * errors as lbm_create.  A slot admitted with nsteps = 0 never runs. */
 int lbm_pool_admit(lbm_pool *pool, const lbm_params *params, int32_t nsteps, int32_t *slot_out);
 
-/* Advances every slot with steps left by min(graph_steps, steps left) steps in
- * one graph launch and waits for it.  finished (nullable, max_slots entries)
- * receives the slots that reached their step count in this call, *nfinished
- * their number.  Returns LBM_OK (also when nothing was running). */
+/* Starts a round without waiting: picks the slots (policy), uploads the slot
+ * table and launches the graph; each picked slot advances by
+ * min(graph_steps, its steps left).  *nlaunched (nullable): slots picked, 0
+ * when nothing has steps left (then nothing is launched).  LBM_E_INVAL when a
+ * round is already in flight. */
+int lbm_pool_launch(lbm_pool *pool, int32_t *nlaunched);
+
+/* Waits for the round in flight (no-op without one) and books its steps.
+ * finished (nullable, max_slots entries) receives the slots that reached
+ * their step count in this round, *nfinished their number. */
+int lbm_pool_wait(lbm_pool *pool, int32_t *finished, int32_t *nfinished);
+
+/* lbm_pool_launch followed by lbm_pool_wait. */
 int lbm_pool_run(lbm_pool *pool, int32_t *finished, int32_t *nfinished);
 
 /* Steps taken and steps still to run of a slot. */
 int lbm_pool_slot_progress(const lbm_pool *pool, int32_t slot, int64_t *steps_done, int64_t *steps_left);
 
-/* Moments of a slot, as lbm_moments(). */
+/* Moments of a slot, as lbm_moments().  LBM_E_INVAL for a slot of the round
+ * in flight. */
 int lbm_pool_moments(lbm_pool *pool, int32_t slot, double *out_host, double *totals);
 
-/* Releases a slot and its arena range. */
+/* Releases a slot and its arena range.  LBM_E_INVAL for a slot of the round
+ * in flight. */
 int lbm_pool_release(lbm_pool *pool, int32_t slot);
 
 int lbm_pool_get_info(const lbm_pool *pool, lbm_pool_info *info);
 
-/* Releases every slot, the graph and the pool (not the caller's arena). */
+/* Waits for everything the pool launched, releases every slot, the graph,
+ * the admission stream and the pool (not the caller's arena). */
 int lbm_pool_destroy(lbm_pool *pool);
 
+/* Message of the last failure on pool, or of the calling thread's last
+ * failed pool call that had no pool (pool = NULL).  Never NULL. */
 const char *lbm_pool_last_error(const lbm_pool *pool);
 
 #ifdef __cplusplus

@@ -638,9 +638,11 @@ namespace {
 
 struct PoolSlot {
     bool used = false;
+    bool in_round = false;  // part of the launched, not yet waited-for round
     lbm_ctx *ctx = nullptr;
     int64_t off = 0, bytes = 0;
     int64_t steps_total = 0, steps_left = 0;
+    int64_t admitted_seq = 0;  // admission order (ties of the SRPT order)
 };
 
 // first-fit allocator over [base, base + size) in 256-byte units
@@ -698,9 +700,13 @@ struct RangeHeap {
 }  // namespace
 
 struct lbm_pool {
-    int storage = 0, max_slots = 0, graph_steps = 1, grid = 8;
-    hipStream_t stream = nullptr;
+    int storage = 0, max_slots = 0, graph_steps = 1, grid = 8, sched = LBM_SCHED_ALL;
+    int64_t fill_cells = 0;
+    hipStream_t stream = nullptr;        // rounds (the captured graph)
+    hipStream_t admit_stream = nullptr;  // admission, moments, release
+    hipEvent_t admitted = nullptr;       // last admission's work, waited for by the next round
     bool own_stream = false;
+    bool in_flight = false;
     char *arena = nullptr;
     int64_t arena_bytes = 0;
     SlotTable *d_table = nullptr;
@@ -708,6 +714,8 @@ struct lbm_pool {
     size_t table_bytes = 0;
     RangeHeap heap;
     std::vector<PoolSlot> slots;
+    std::vector<int> round;  // slots of the launched round
+    int64_t seq = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::string err = "no error";
@@ -733,13 +741,47 @@ void pool_free(lbm_pool *p)
 {
     if (!p) return;
     if (p->stream) (void)hipStreamSynchronize(p->stream);
+    if (p->admit_stream) (void)hipStreamSynchronize(p->admit_stream);
     for (auto &s : p->slots)
         if (s.used && s.ctx) lbm_destroy(s.ctx);
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->h_table) (void)hipHostFree(p->h_table);
+    if (p->admitted) (void)hipEventDestroy(p->admitted);
+    if (p->admit_stream) (void)hipStreamDestroy(p->admit_stream);
     if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
     delete p;
+}
+
+bool slot_ok(const lbm_pool *p, int32_t slot) { return p && slot >= 0 && slot < p->max_slots && p->slots[slot].used; }
+
+// The slots the next round advances.  LBM_SCHED_ALL: every slot with steps
+// left (processor sharing).  LBM_SCHED_SRPT: slots in order of remaining work
+// (fluid cells x steps left, admission order on ties), the first always, the
+// next ones while the cells per step stay within max(fill_cells, cells of the
+// first): small solves finish first and in few launches, and a launch is
+// never slowed down by more than what fills the device anyway.
+std::vector<int> pick_round(const lbm_pool *p)
+{
+    std::vector<int> run;
+    for (int i = 0; i < p->max_slots; ++i)
+        if (p->slots[i].used && p->slots[i].steps_left > 0) run.push_back(i);
+    if (p->sched != LBM_SCHED_SRPT || run.size() < 2) return run;
+    auto work = [&](int i) { return p->slots[i].ctx->fluid_cells * p->slots[i].steps_left; };
+    std::sort(run.begin(), run.end(), [&](int a, int b) {
+        const int64_t wa = work(a), wb = work(b);
+        return wa != wb ? wa < wb : p->slots[a].admitted_seq < p->slots[b].admitted_seq;
+    });
+    const int64_t cap = std::max(p->fill_cells, p->slots[run[0]].ctx->desc.n);
+    std::vector<int> out;
+    int64_t cells = 0;
+    for (int i : run) {
+        const int64_t c = p->slots[i].ctx->desc.n;
+        if (!out.empty() && cells + c > cap) continue;
+        out.push_back(i);
+        cells += c;
+    }
+    return out;
 }
 
 }  // namespace
@@ -752,14 +794,16 @@ int64_t lbm_pool_overhead_bytes(int32_t max_slots)
     return align_up((int64_t)slot_table_bytes(max_slots));
 }
 
-int lbm_pool_create(int32_t storage, int32_t max_slots, int32_t graph_steps, void *dev_arena, int64_t arena_bytes,
-                    void *hip_stream, lbm_pool **out)
+int lbm_pool_create(int32_t storage, int32_t max_slots, int32_t graph_steps, int32_t sched, int64_t fill_cells,
+                    void *dev_arena, int64_t arena_bytes, void *hip_stream, lbm_pool **out)
 {
     if (!out) return fail(nullptr, LBM_E_INVAL, "out is NULL");
     *out = nullptr;
     if (storage < LBM_STORE_FP64 || storage > LBM_STORE_FP16_SHIFTED) return fail(nullptr, LBM_E_INVAL, "unknown storage");
     if (max_slots < 1 || max_slots > kMaxSlots) return fail(nullptr, LBM_E_INVAL, "max_slots out of range");
     if (graph_steps < 1 || graph_steps > 4096) return fail(nullptr, LBM_E_INVAL, "graph_steps out of range");
+    if (sched != LBM_SCHED_ALL && sched != LBM_SCHED_SRPT) return fail(nullptr, LBM_E_INVAL, "unknown scheduling policy");
+    if (fill_cells < 0) return fail(nullptr, LBM_E_INVAL, "fill_cells must be >= 0");
     if (!dev_arena || reinterpret_cast<uintptr_t>(dev_arena) % kAlign != 0)
         return fail(nullptr, LBM_E_INVAL, "dev_arena must be a 256-byte aligned device pointer");
     const int64_t head = lbm_pool_overhead_bytes(max_slots);
@@ -770,6 +814,7 @@ int lbm_pool_create(int32_t storage, int32_t max_slots, int32_t graph_steps, voi
     p->storage = storage;
     p->max_slots = max_slots;
     p->graph_steps = graph_steps;
+    p->sched = sched;
     p->arena = static_cast<char *>(dev_arena);
     p->arena_bytes = arena_bytes;
     p->table_bytes = slot_table_bytes(max_slots);
@@ -784,9 +829,15 @@ int lbm_pool_create(int32_t storage, int32_t max_slots, int32_t graph_steps, voi
     if (hip_stream) {
         p->stream = static_cast<hipStream_t>(hip_stream);
     } else {
-        if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess)
-            return bail(LBM_E_DEVICE, "hipStreamCreateWithFlags failed");
+        const hipError_t e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return bail(LBM_E_DEVICE, std::string("pool stream: ") + hipGetErrorString(e));
         p->own_stream = true;
+    }
+    {
+        hipError_t e = hipStreamCreateWithFlags(&p->admit_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return bail(LBM_E_DEVICE, std::string("admission stream: ") + hipGetErrorString(e));
+        e = hipEventCreateWithFlags(&p->admitted, hipEventDisableTiming);
+        if (e != hipSuccess) return bail(LBM_E_DEVICE, std::string("admission event: ") + hipGetErrorString(e));
     }
     if (hipHostMalloc(reinterpret_cast<void **>(&p->h_table), p->table_bytes, hipHostMallocDefault) != hipSuccess)
         return bail(LBM_E_DEVICE, "hipHostMalloc failed");
@@ -808,6 +859,8 @@ int lbm_pool_create(int32_t storage, int32_t max_slots, int32_t graph_steps, voi
         grid = std::min(grid, kMaxGrid);
         p->grid = std::max(8, grid / 8 * 8);
     }
+    // default fill: four row blocks per resident workgroup of the persistent grid
+    p->fill_cells = fill_cells > 0 ? fill_cells : (int64_t)p->grid * kBlockThreads * 4;
     // capture graph_steps launches of the batched step; the slot table (read
     // by the kernel at run time) decides which slots each launch advances
     if (hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
@@ -843,33 +896,39 @@ int lbm_pool_admit(lbm_pool *p, const lbm_params *params, int32_t nsteps, int32_
     if (slot < 0) return pool_fail(p, LBM_E_NOMEM, "no free slot");
     const int64_t off = p->heap.alloc(need);
     if (off < 0) return pool_fail(p, LBM_E_NOMEM, "no free range of " + std::to_string(need) + " bytes");
+    // created on the admission stream: overlaps a round in flight, whose
+    // slots own disjoint arena ranges
     lbm_ctx *ctx = nullptr;
-    const int rc = lbm_create(params, p->arena + off, need, p->stream, &ctx);
+    const int rc = lbm_create(params, p->arena + off, need, p->admit_stream, &ctx);
     if (rc != LBM_OK) {
         p->heap.release(off, need);
         return pool_fail(p, rc, lbm_last_error(nullptr));
     }
+    POOL_TRY(p, hipEventRecord(p->admitted, p->admit_stream));
     PoolSlot &s = p->slots[slot];
     s.used = true;
+    s.in_round = false;
     s.ctx = ctx;
     s.off = off;
     s.bytes = need;
     s.steps_total = nsteps;
     s.steps_left = nsteps;
+    s.admitted_seq = p->seq++;
     *slot_out = slot;
     return LBM_OK;
 }
 
-int lbm_pool_run(lbm_pool *p, int32_t *finished, int32_t *nfinished)
+int lbm_pool_launch(lbm_pool *p, int32_t *nlaunched)
 {
     if (!p) return fail(nullptr, LBM_E_INVAL, "pool is NULL");
-    if (nfinished) *nfinished = 0;
+    if (nlaunched) *nlaunched = 0;
+    if (p->in_flight) return pool_fail(p, LBM_E_INVAL, "a round is already in flight");
+    const std::vector<int> run = pick_round(p);
+    if (run.empty()) return LBM_OK;
     SlotTable *t = p->h_table;
-    int n = 0, blocks = 0;
-    std::vector<int> order;
-    for (int i = 0; i < p->max_slots; ++i) {
-        const PoolSlot &s = p->slots[i];
-        if (!s.used || s.steps_left <= 0) continue;
+    int blocks = 0, n = 0;
+    for (int i : run) {
+        PoolSlot &s = p->slots[i];
         SlotDesc d = s.ctx->desc;
         d.parity0 = (int32_t)(s.ctx->steps & 1);
         d.steps_todo = (int32_t)std::min<int64_t>(p->graph_steps, s.steps_left);
@@ -877,35 +936,59 @@ int lbm_pool_run(lbm_pool *p, int32_t *finished, int32_t *nfinished)
         t->slot[n] = d;
         t->block_start[n] = blocks;
         blocks += d.blocks;
-        order.push_back(i);
         ++n;
     }
-    if (n == 0) return LBM_OK;
     t->nslots = n;
     t->block_start[n] = blocks;
     t->total_blocks = blocks;
+    POOL_TRY(p, hipStreamWaitEvent(p->stream, p->admitted, 0));
     POOL_TRY(p, hipMemcpyAsync(p->d_table, t, slot_table_bytes(n), hipMemcpyHostToDevice, p->stream));
     POOL_TRY(p, hipGraphLaunch(p->exec, p->stream));
-    POOL_TRY(p, hipStreamSynchronize(p->stream));
+    for (int i : run) p->slots[i].in_round = true;
+    p->round = run;
+    p->in_flight = true;
+    if (nlaunched) *nlaunched = n;
+    return LBM_OK;
+}
+
+int lbm_pool_wait(lbm_pool *p, int32_t *finished, int32_t *nfinished)
+{
+    if (!p) return fail(nullptr, LBM_E_INVAL, "pool is NULL");
+    if (nfinished) *nfinished = 0;
+    if (!p->in_flight) return LBM_OK;
+    const hipError_t e = hipStreamSynchronize(p->stream);
+    p->in_flight = false;
     int nf = 0;
-    for (int k = 0; k < n; ++k) {
-        PoolSlot &s = p->slots[order[k]];
+    for (int i : p->round) {
+        PoolSlot &s = p->slots[i];
+        s.in_round = false;
+        if (e != hipSuccess) continue;
         const int64_t adv = std::min<int64_t>(p->graph_steps, s.steps_left);
         s.ctx->steps += adv;
         s.steps_left -= adv;
         if (s.steps_left == 0) {
-            if (finished) finished[nf] = order[k];
+            if (finished) finished[nf] = i;
             ++nf;
         }
     }
+    p->round.clear();
+    if (e != hipSuccess) return pool_fail(p, LBM_E_DEVICE, std::string("round failed: ") + hipGetErrorString(e));
     if (nfinished) *nfinished = nf;
     return LBM_OK;
 }
 
+int lbm_pool_run(lbm_pool *p, int32_t *finished, int32_t *nfinished)
+{
+    if (!p) return fail(nullptr, LBM_E_INVAL, "pool is NULL");
+    if (nfinished) *nfinished = 0;
+    const int rc = lbm_pool_launch(p, nullptr);
+    if (rc != LBM_OK) return rc;
+    return lbm_pool_wait(p, finished, nfinished);
+}
+
 int lbm_pool_slot_progress(const lbm_pool *p, int32_t slot, int64_t *steps_done, int64_t *steps_left)
 {
-    if (!p || slot < 0 || slot >= p->max_slots || !p->slots[slot].used)
-        return fail(nullptr, LBM_E_INVAL, "invalid pool or slot");
+    if (!slot_ok(p, slot)) return fail(nullptr, LBM_E_INVAL, "invalid pool or slot");
     if (steps_done) *steps_done = p->slots[slot].steps_total - p->slots[slot].steps_left;
     if (steps_left) *steps_left = p->slots[slot].steps_left;
     return LBM_OK;
@@ -913,8 +996,8 @@ int lbm_pool_slot_progress(const lbm_pool *p, int32_t slot, int64_t *steps_done,
 
 int lbm_pool_moments(lbm_pool *p, int32_t slot, double *out_host, double *totals)
 {
-    if (!p || slot < 0 || slot >= p->max_slots || !p->slots[slot].used)
-        return fail(nullptr, LBM_E_INVAL, "invalid pool or slot");
+    if (!slot_ok(p, slot)) return fail(nullptr, LBM_E_INVAL, "invalid pool or slot");
+    if (p->slots[slot].in_round) return pool_fail(p, LBM_E_INVAL, "slot is part of the round in flight");
     const int rc = lbm_moments(p->slots[slot].ctx, out_host, totals);
     if (rc != LBM_OK) p->err = lbm_last_error(p->slots[slot].ctx);
     return rc;
@@ -922,8 +1005,8 @@ int lbm_pool_moments(lbm_pool *p, int32_t slot, double *out_host, double *totals
 
 int lbm_pool_release(lbm_pool *p, int32_t slot)
 {
-    if (!p || slot < 0 || slot >= p->max_slots || !p->slots[slot].used)
-        return fail(nullptr, LBM_E_INVAL, "invalid pool or slot");
+    if (!slot_ok(p, slot)) return fail(nullptr, LBM_E_INVAL, "invalid pool or slot");
+    if (p->slots[slot].in_round) return pool_fail(p, LBM_E_INVAL, "slot is part of the round in flight");
     PoolSlot &s = p->slots[slot];
     const int rc = lbm_destroy(s.ctx);
     p->heap.release(s.off, s.bytes);
@@ -943,6 +1026,9 @@ int lbm_pool_get_info(const lbm_pool *p, lbm_pool_info *info)
         info->running += s.used && s.steps_left > 0;
     }
     info->graph_steps = p->graph_steps;
+    info->sched = p->sched;
+    info->in_flight = p->in_flight;
+    info->fill_cells = p->fill_cells;
     info->arena_bytes = p->arena_bytes;
     info->free_bytes = p->heap.total();
     info->largest_free = p->heap.largest();

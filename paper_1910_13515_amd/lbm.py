@@ -37,8 +37,9 @@ LBM_FACE_NEUMANN = 2
 
 EXPORTED = ["lbm_version", "lbm_velocities", "lbm_required_bytes", "lbm_create", "lbm_step", "lbm_moments",
             "lbm_get_state", "lbm_set_state", "lbm_get_info", "lbm_destroy", "lbm_last_error",
-            "lbm_pool_overhead_bytes", "lbm_pool_create", "lbm_pool_admit", "lbm_pool_run", "lbm_pool_slot_progress",
-            "lbm_pool_moments", "lbm_pool_release", "lbm_pool_get_info", "lbm_pool_destroy", "lbm_pool_last_error"]
+            "lbm_pool_overhead_bytes", "lbm_pool_create", "lbm_pool_admit", "lbm_pool_launch", "lbm_pool_wait",
+            "lbm_pool_run", "lbm_pool_slot_progress", "lbm_pool_moments", "lbm_pool_release", "lbm_pool_get_info",
+            "lbm_pool_destroy", "lbm_pool_last_error"]
 
 
 class lbm_params(ctypes.Structure):
@@ -70,10 +71,16 @@ class lbm_info(ctypes.Structure):
     ]
 
 
+LBM_SCHED_ALL = 0
+LBM_SCHED_SRPT = 1
+SCHED = {"all": LBM_SCHED_ALL, "srpt": LBM_SCHED_SRPT}
+
+
 class lbm_pool_info(ctypes.Structure):
     _fields_ = [
         ("max_slots", ctypes.c_int32), ("active", ctypes.c_int32), ("running", ctypes.c_int32),
-        ("graph_steps", ctypes.c_int32), ("arena_bytes", ctypes.c_int64), ("free_bytes", ctypes.c_int64),
+        ("graph_steps", ctypes.c_int32), ("sched", ctypes.c_int32), ("in_flight", ctypes.c_int32),
+        ("fill_cells", ctypes.c_int64), ("arena_bytes", ctypes.c_int64), ("free_bytes", ctypes.c_int64),
         ("largest_free", ctypes.c_int64),
     ]
 
@@ -88,6 +95,10 @@ def load() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    # torch first: the library's HIP runtime dependency must resolve to the
+    # runtime torch has loaded, which owns the device arenas handed to it (a
+    # second HIP runtime in the process does not see the device)
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     L.lbm_version.restype = i32
@@ -114,9 +125,13 @@ def load() -> ctypes.CDLL:
     L.lbm_pool_overhead_bytes.restype = i64
     L.lbm_pool_overhead_bytes.argtypes = [i32]
     L.lbm_pool_create.restype = ctypes.c_int
-    L.lbm_pool_create.argtypes = [i32, i32, i32, vp, i64, vp, ctypes.POINTER(vp)]
+    L.lbm_pool_create.argtypes = [i32, i32, i32, i32, i64, vp, i64, vp, ctypes.POINTER(vp)]
     L.lbm_pool_admit.restype = ctypes.c_int
     L.lbm_pool_admit.argtypes = [vp, ctypes.POINTER(lbm_params), i32, ctypes.POINTER(i32)]
+    L.lbm_pool_launch.restype = ctypes.c_int
+    L.lbm_pool_launch.argtypes = [vp, ctypes.POINTER(i32)]
+    L.lbm_pool_wait.restype = ctypes.c_int
+    L.lbm_pool_wait.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.lbm_pool_run.restype = ctypes.c_int
     L.lbm_pool_run.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.lbm_pool_slot_progress.restype = ctypes.c_int

@@ -59,7 +59,7 @@ class Pool:
     """A serving pool over a torch-owned device arena."""
 
     def __init__(self, arena_bytes: int, storage: str = "fp32s", max_slots: int = 64, graph_steps: int = 32,
-                 stream=None):
+                 sched: str = "srpt", fill_cells: int = 0, stream=None):
         import torch
         L = _lib()
         self.storage = storage
@@ -68,8 +68,9 @@ class Pool:
         base = (self.arena.data_ptr() + 255) // 256 * 256
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p()
-        code = L.lbm_pool_create(lbm.STORAGE[storage], max_slots, graph_steps, ctypes.c_void_p(base),
-                                 int(arena_bytes), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        code = L.lbm_pool_create(lbm.STORAGE[storage], max_slots, graph_steps, lbm.SCHED[sched], int(fill_cells),
+                                 ctypes.c_void_p(base), int(arena_bytes), ctypes.c_void_p(self.stream.cuda_stream),
+                                 ctypes.byref(h))
         if code != 0:
             raise lbm.LbmError(code, L.lbm_pool_last_error(None).decode())
         self.h = h
@@ -91,8 +92,20 @@ class Pool:
         self._check(code)
         return slot.value
 
+    def launch(self) -> int:
+        """Start a round without waiting; number of slots it advances."""
+        n = ctypes.c_int32()
+        self._check(_lib().lbm_pool_launch(self.h, ctypes.byref(n)))
+        return n.value
+
+    def wait(self):
+        """Wait for the round in flight; slots that reached their step count."""
+        nf = ctypes.c_int32()
+        self._check(_lib().lbm_pool_wait(self.h, self._finished, ctypes.byref(nf)))
+        return [self._finished[k] for k in range(nf.value)]
+
     def run(self):
-        """One round (graph_steps steps of every running slot); finished slots."""
+        """One round, waited for; finished slots."""
         nf = ctypes.c_int32()
         self._check(_lib().lbm_pool_run(self.h, self._finished, ctypes.byref(nf)))
         return [self._finished[k] for k in range(nf.value)]
@@ -167,24 +180,38 @@ def _cells(req):
     return req.shape[0] * req.shape[1] * req.shape[2]
 
 
-def serve_batched(trace, pool: Pool, keep_fields: bool = False, realtime: bool = True):
+def serve_batched(trace, pool, keep_fields: bool = False, realtime: bool = True):
     """Continuous batching over a pool.  With realtime, requests become
     visible at their arrival times (relative to the start); otherwise all are
-    visible at once.  Returns (outcomes, summary)."""
+    visible at once.  Arrivals are admitted in arrival order as soon as their
+    footprint fits, also while a round is in flight; as soon as a round ends
+    the next one is launched, and the finished solves are read back and
+    released while it runs.  Returns (outcomes, summary)."""
     pending = collections.deque(sorted(trace, key=lambda r: r.arrival))
     waiting = collections.deque()
     active = {}
     outcomes = {}
     t0 = time.perf_counter()
     now = lambda: time.perf_counter() - t0  # noqa: E731
+    in_flight = False
+
+    def retire(slots):
+        for slot in slots:
+            r = active.pop(slot)
+            o = outcomes[r.rid]
+            f, tot = pool.moments(slot, _cells(r), fields=keep_fields)
+            o.done = now()
+            o.totals, o.fields = tot, f
+            pool.release(slot)
+
     while pending or waiting or active:
         t = now()
         while pending and (not realtime or pending[0].arrival <= t):
             r = pending.popleft()
             waiting.append(r)
             outcomes[r.rid] = Outcome(r.rid, r.kind, _cells(r), r.steps, r.arrival if realtime else 0.0)
-        # admission in arrival order, by footprint
-        finished = []
+        # admission in arrival order, by footprint (overlaps a round in flight)
+        zero = []
         while waiting:
             slot = pool.admit(waiting[0])
             if slot is None:
@@ -193,20 +220,19 @@ def serve_batched(trace, pool: Pool, keep_fields: bool = False, realtime: bool =
             active[slot] = r
             outcomes[r.rid].admitted = now()
             if r.steps == 0:
-                finished.append(slot)
-        if active:
-            if not finished:
-                finished = pool.run()
-            for slot in finished:
-                r = active.pop(slot)
-                o = outcomes[r.rid]
-                f, tot = pool.moments(slot, _cells(r), fields=keep_fields)
-                o.done = now()
-                o.totals, o.fields = tot, f
-                pool.release(slot)
-        elif waiting:
+                zero.append(slot)
+        retire(zero)
+        if not in_flight and active:
+            in_flight = pool.launch() > 0
+            if not in_flight:
+                raise RuntimeError("admitted solves with steps left, but the pool launched nothing")
+        if in_flight:
+            finished = pool.wait()
+            in_flight = pool.launch() > 0  # next round first, then read back
+            retire(finished)
+        elif waiting and not active:
             raise RuntimeError(f"request {waiting[0].rid} does not fit in an empty pool")
-        elif pending:
+        elif pending and not active:
             time.sleep(max(0.0, pending[0].arrival - now()))
     outs = [outcomes[r.rid] for r in trace]
     t_first = min(o.arrival for o in outs)

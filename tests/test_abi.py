@@ -89,18 +89,27 @@ def test_pool_arguments_validated_without_device(L):
     assert head > 0 and head % 256 == 0
     pool = ctypes.c_void_p()
     ok = ctypes.c_void_p(1 << 20)  # aligned, never dereferenced: every call below fails first
-    assert L.lbm_pool_create(1, 8, 4, ok, 1 << 30, None, None) == lbm.LBM_E_INVAL
-    assert L.lbm_pool_create(7, 8, 4, ok, 1 << 30, None, ctypes.byref(pool)) == lbm.LBM_E_INVAL
-    assert L.lbm_pool_create(1, 0, 4, ok, 1 << 30, None, ctypes.byref(pool)) == lbm.LBM_E_INVAL
-    assert L.lbm_pool_create(1, 8, 0, ok, 1 << 30, None, ctypes.byref(pool)) == lbm.LBM_E_INVAL
-    assert L.lbm_pool_create(1, 8, 4, ctypes.c_void_p((1 << 20) + 8), 1 << 30, None,
-                             ctypes.byref(pool)) == lbm.LBM_E_INVAL
-    assert L.lbm_pool_create(1, 8, 4, ok, head - 256, None, ctypes.byref(pool)) == lbm.LBM_E_NOMEM
+    big = 1 << 30
+
+    def create(storage=1, slots=8, k=4, sched=1, fill=0, arena=ok, nbytes=big, out=True):
+        return L.lbm_pool_create(storage, slots, k, sched, fill, arena, nbytes, None,
+                                 ctypes.byref(pool) if out else None)
+
+    assert create(out=False) == lbm.LBM_E_INVAL
+    assert create(storage=7) == lbm.LBM_E_INVAL
+    assert create(slots=0) == lbm.LBM_E_INVAL
+    assert create(k=0) == lbm.LBM_E_INVAL
+    assert create(sched=9) == lbm.LBM_E_INVAL
+    assert create(fill=-1) == lbm.LBM_E_INVAL
+    assert create(arena=ctypes.c_void_p((1 << 20) + 8)) == lbm.LBM_E_INVAL
+    assert create(nbytes=head - 256) == lbm.LBM_E_NOMEM
     assert not pool.value
     slot = ctypes.c_int32()
     p = lbm.make_params((16, 8, 1), tau=0.6)
     assert L.lbm_pool_admit(None, ctypes.byref(p), 1, ctypes.byref(slot)) == lbm.LBM_E_INVAL
     assert L.lbm_pool_run(None, None, None) == lbm.LBM_E_INVAL
+    assert L.lbm_pool_launch(None, None) == lbm.LBM_E_INVAL
+    assert L.lbm_pool_wait(None, None, None) == lbm.LBM_E_INVAL
     assert L.lbm_pool_moments(None, 0, None, None) == lbm.LBM_E_INVAL
     assert L.lbm_pool_release(None, 0) == lbm.LBM_E_INVAL
     assert L.lbm_pool_destroy(None) == lbm.LBM_E_INVAL

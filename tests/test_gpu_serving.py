@@ -21,14 +21,17 @@ def _first(kind, seed=3, **kw):
     return next(r for r in _trace(seed, 16, **kw) if r.kind == kind)
 
 
-@pytest.mark.parametrize("storage", ["fp64", "fp32s", "fp16s"])
-def test_mix_equals_alone_bitwise(storage):
+@pytest.mark.parametrize("storage,sched", [("fp64", "all"), ("fp64", "srpt"), ("fp32s", "srpt"), ("fp16s", "srpt"),
+                                           ("fp32s", "all")])
+def test_mix_equals_alone_bitwise(storage, sched):
     from paper_1910_13515_amd import serve
     trace = _trace(11, 9)
     fps = [serve.footprint(r, storage) for r in trace]
     # room for about half of them at once: admission waits, slots are reused
     room = max(sum(fps) // 2, max(fps)) + (1 << 20)
-    pool = serve.Pool(lbm.load().lbm_pool_overhead_bytes(4) + room, storage=storage, max_slots=4, graph_steps=8)
+    # a small SRPT fill bound so that rounds really leave slots waiting
+    pool = serve.Pool(lbm.load().lbm_pool_overhead_bytes(4) + room, storage=storage, max_slots=4, graph_steps=8,
+                      sched=sched, fill_cells=3000)
     outs, summary = serve.serve_batched(trace, pool, keep_fields=True, realtime=False)
     assert summary["requests"] == len(trace)
     inf = pool.info()
@@ -58,8 +61,17 @@ def test_admission_by_footprint_and_release():
     import ctypes
     slot = ctypes.c_int32()
     assert L.lbm_pool_admit(pool.h, ctypes.byref(p), 1, ctypes.byref(slot)) == lbm.LBM_E_INVAL
-    done = []
-    for _ in range(3):
+    # a round in flight: its slots cannot be read or released, admission goes on
+    assert pool.launch() == 2
+    assert pool.info().in_flight == 1
+    with pytest.raises(lbm.LbmError):
+        pool.moments(a, 12 ** 3)
+    with pytest.raises(lbm.LbmError):
+        pool.release(b)
+    with pytest.raises(lbm.LbmError):
+        pool.launch()
+    done = pool.wait()
+    for _ in range(2):
         done += pool.run()
     assert sorted(done) == sorted([a, b])
     assert pool.run() == []  # nothing running: a no-op
@@ -67,6 +79,25 @@ def test_admission_by_footprint_and_release():
     c = pool.admit(req)
     assert c is not None
     assert pool.info().active == 2
+    pool.close()
+
+
+def test_admission_during_round_matches_alone():
+    from paper_1910_13515_amd import serve
+    first = _first("box", seed=7, box_cells=(14, 14), steps=(24, 24))
+    late = _first("tube", seed=8, tube_cells=(150, 150), steps=(17, 17))
+    pool = serve.Pool(256 << 20, storage="fp32s", max_slots=4, graph_steps=8, sched="all")
+    a = pool.admit(first)
+    assert pool.launch() == 1
+    b = pool.admit(late)  # created on the admission stream while the round runs
+    fin = pool.wait()
+    while a not in fin or b not in fin:
+        assert pool.launch() >= 1
+        fin += pool.wait()
+    for slot, r in ((a, first), (b, late)):
+        f, tot = pool.moments(slot, int(np.prod(r.shape)), fields=True)
+        f1, t1 = serve.solve_alone(r, "fp32s")
+        assert np.array_equal(f, f1) and np.array_equal(tot, t1), r.rid
     pool.close()
 
 

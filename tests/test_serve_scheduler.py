@@ -17,6 +17,8 @@ class FakePool:
         self.peak = 0
         self.runs = 0
         self.admit_order = []
+        self.round = []
+        self.in_flight = False
 
     def admit(self, req):
         need = self.footprint(req)
@@ -30,21 +32,31 @@ class FakePool:
         self.admit_order.append(req.rid)
         return s
 
-    def run(self):
-        self.runs += 1
+    def launch(self):
+        assert not self.in_flight
+        self.round = [s for s, v in self.slots.items() if v[2] > 0]
+        self.in_flight = bool(self.round)
+        if self.in_flight:
+            self.runs += 1
+        return len(self.round)
+
+    def wait(self):
         done = []
-        for s, v in self.slots.items():
-            if v[2] > 0:
-                v[2] -= min(self.k, v[2])
-                if v[2] == 0:
-                    done.append(s)
+        for s in self.round:
+            v = self.slots[s]
+            v[2] -= min(self.k, v[2])
+            if v[2] == 0:
+                done.append(s)
+        self.round, self.in_flight = [], False
         return done
 
     def moments(self, slot, n, fields=False):
+        assert slot not in self.round
         req = self.slots[slot][0]
         return None, np.array([float(req.rid), n, 0.0, 0.0, 0.0])
 
     def release(self, slot):
+        assert slot not in self.round
         self.used -= self.slots.pop(slot)[1]
 
 
