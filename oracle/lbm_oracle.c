@@ -495,8 +495,12 @@ int64_t orc_init(const orc_params *p, const double *rho, const double *u, const 
  * macroscopic variables, the Maxwell-Boltzmann targets, the multipliers by
  * Newton from the stored ones, f^eq and g^eq, the Knudsen sensor and the
  * relaxation factor, and write the BGK-relaxed populations.  Boundary and
- * solid cells are copied unchanged.  iters_out / eps_out (length N, or NULL)
- * receive per-cell diagnostics (-1 / NaN outside fluid cells). */
+ * solid cells are copied unchanged.  A fluid cell whose Newton solve fails
+ * (warm start, then cold start) is not collided: its gathered populations are
+ * written unchanged and its multipliers kept; it is counted in st->failed and
+ * in no alpha branch.  iters_out / eps_out (length N, or NULL) receive
+ * per-cell diagnostics (-1 / NaN outside fluid cells, NaN for eps of a failed
+ * cell). */
 void orc_step(const orc_params *p, const double *f, const double *g, const double *lam, double *fo, double *go,
               double *lamo, int32_t *iters_out, double *eps_out, orc_stats *st)
 {
@@ -546,11 +550,23 @@ void orc_step(const orc_params *p, const double *f, const double *g, const doubl
             cold_guess(u, T, l);
             it2 = newton(m, l, feq, p->newton_tol, p->newton_maxit > 100 ? p->newton_maxit : 100);
             if (it2 < 0) {
+                /* reading: where no multipliers reproduce the 13 targets the
+                 * cell is not collided; its gathered populations are stored
+                 * as they are and its multipliers are kept (the paper gives
+                 * no rule; this one conserves every moment of the cell) */
                 s_fail += 1;
-                it = p->newton_maxit;
-            } else {
-                it = it2;
+                s_it += p->newton_maxit;
+                if (p->newton_maxit > s_max) s_max = p->newton_maxit;
+                for (i = 0; i < NQ; ++i) {
+                    fo[i * n + c] = fi[i];
+                    go[i * n + c] = gi[i];
+                }
+                for (k = 0; k < NL; ++k) lamo[k * n + c] = lam[k * n + c];
+                if (iters_out) iters_out[c] = p->newton_maxit;
+                if (eps_out) eps_out[c] = NAN;
+                continue;
             }
+            it = it2;
         }
         s_it += it;
         if (it > s_max) s_max = it;

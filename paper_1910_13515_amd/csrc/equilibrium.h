@@ -285,6 +285,16 @@ __device__ __forceinline__ int solve_multipliers(const C u[3], C T, C lam[kM], C
 #pragma unroll
         for (int k = 0; k < kM; ++k) lam[k] -= d[k];
     }
+    if (status == kFailed) {
+        // no equilibrium: leave finite values behind (the caller does not
+        // relax such a cell, and omega = 0 times a finite difference is 0);
+        // zero residuals keep the invariant projection a no-op
+        f0 = C(0);
+#pragma unroll
+        for (int p = 0; p < kPairs; ++p) fp[p] = fm[p] = C(0);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) resid[k] = C(0);
+    }
     iters = status == kFailed ? maxit : it;
     return status;
 }

@@ -341,21 +341,27 @@ __device__ __forceinline__ void update_cell(const SlotDesc &d, const S *src, S *
     const C eps = eps_sum<S, C>(d, rho, f0, fp, fm, pk, VelSeq{}) * C(1.0 / kQ);
     int br = 0;
     if (d.kn_relax) br = (eps < C(1e-2)) ? 0 : (eps < C(1e-1)) ? 1 : (eps < C(1)) ? 2 : 3;
-    const C omega = C(br == 0 ? d.omega[0] : br == 1 ? d.omega[1] : br == 2 ? d.omega[2] : d.omega[3]);
+    // a cell whose multipliers were not found is not collided (omega = 0
+    // against the finite values the solver leaves): gathered values stored
+    // unchanged, multipliers kept for the next warm start
+    const bool failed = status == kFailed;
+    const C omega = failed ? C(0) : C(br == 0 ? d.omega[0] : br == 1 ? d.omega[1] : br == 2 ? d.omega[2] : d.omega[3]);
     const C dT = C(d.delta) * T;
 
     relax_all<S, C>(d, (gbyte *)dst, nS64, cellS, rho, dT, omega, f0, fp, fm, pk, VelSeq{});
+    if (!failed) {
 #pragma unroll
-    for (int k = 0; k < kM; ++k) gstore<C>(lamb + (uint64_t)k * nC64, cellC, lam[k]);
+        for (int k = 0; k < kM; ++k) gstore<C>(lamb + (uint64_t)k * nC64, cellC, lam[k]);
+    }
 
     acc[0] += iters;
     acc[1] = iters > acc[1] ? iters : acc[1];
-    acc[2] += status == kFailed;
+    acc[2] += failed;
     acc[3] += status == kConvergedCold;
-    acc[4] += br == 0;
-    acc[5] += br == 1;
-    acc[6] += br == 2;
-    acc[7] += br == 3;
+    acc[4] += !failed && br == 0;
+    acc[5] += !failed && br == 1;
+    acc[6] += !failed && br == 2;
+    acc[7] += !failed && br == 3;
 }
 
 // Locate the slot that owns logical block b (uniform across the block).
@@ -538,10 +544,15 @@ __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const 
     if (d.kn_relax) br = (eps < C(1e-2)) ? 0 : (eps < C(1e-1)) ? 1 : (eps < C(1)) ? 2 : 3;
     const C o0 = uniform(C(d.omega[0])), o1 = uniform(C(d.omega[1])), o2 = uniform(C(d.omega[2])),
             o3 = uniform(C(d.omega[3]));
+    // a cell whose multipliers were not found is not collided (omega = 0
+    // against the finite values the solver leaves): gathered values stored
+    // unchanged, multipliers kept for the next warm start
+    const bool failed = status == kFailed;
     C omega = o0;
     omega = br == 1 ? o1 : omega;
     omega = br == 2 ? o2 : omega;
     omega = br == 3 ? o3 : omega;
+    omega = failed ? C(0) : omega;
     const C dT = C(d.delta) * T;
     __asm__ volatile("" ::: "memory");
 #pragma unroll
@@ -553,17 +564,19 @@ __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const 
         pk.put(i, hf + omega * ((feq - C(d.shift_w[i])) - hf));
         pk.put(kQ + i, hg + omega * ((geq - C(d.shift_w[kQ + i])) - hg));
     }
+    if (!failed) {
 #pragma unroll
-    for (int k = 0; k < kM; ++k) gstore<C>(lamb + (uint64_t)k * nS64, cellS, lam[k]);
+        for (int k = 0; k < kM; ++k) gstore<C>(lamb + (uint64_t)k * nS64, cellS, lam[k]);
+    }
 
     acc[0] += iters;
     acc[1] = iters > acc[1] ? iters : acc[1];
-    acc[2] += status == kFailed;
+    acc[2] += failed;
     acc[3] += status == kConvergedCold;
-    acc[4] += br == 0;
-    acc[5] += br == 1;
-    acc[6] += br == 2;
-    acc[7] += br == 3;
+    acc[4] += !failed && br == 0;
+    acc[5] += !failed && br == 1;
+    acc[6] += !failed && br == 2;
+    acc[7] += !failed && br == 3;
 }
 
 }  // namespace f32

@@ -222,9 +222,49 @@ def test_newton_failure_is_reported(orc, lbm):
     st, code = lbm.lbm_step(s.ctx, 1, with_stats=True)
     assert code == lbm.LBM_E_NEWTON
     assert st.failed == n
+    assert sum(st.alpha_hist) == 0  # failed cells are in no alpha branch
     o.set_state(f, G.reshape(-1), lam)
     o.step(1)
     assert o.stats.failed == n
+    # no collision where no equilibrium exists: in a uniform periodic state the
+    # gathered populations are the stored ones, so the state is unchanged, bit
+    # for bit, on both sides, and the multipliers are kept
+    f1, g1, lam1 = s.get_state()
+    assert np.array_equal(f1, f) and np.array_equal(g1, G.reshape(-1)) and np.array_equal(lam1, lam)
+    assert np.array_equal(o.f, f) and np.array_equal(o.g, G.reshape(-1)) and np.array_equal(o.lam, lam)
+    s.close()
+
+
+def test_cells_without_equilibrium_match_oracle(orc, lbm):
+    """A cold slab with no 13-moment equilibrium inside a warm periodic box:
+    the GPU and the oracle fail on the same cells, leave them uncollided and
+    agree on every population and multiplier."""
+    shape = (16, 4, 4)
+    nx = shape[0]
+    n = int(np.prod(shape))
+    rho, u, T = inputs.uniform_fields(n, 1.0, [0.1, 0.0, 0.0], 0.5)
+    o = orc.Oracle(*shape, gamma=1.4, tau=0.6, newton_tol=1e-13)
+    o.init(rho, u, T)
+    f, g, lam = o.f.copy(), o.g.copy(), o.lam.copy()
+    c = orc.velocities()
+    q = (c ** 2).sum(1)
+    F = f.reshape(39, n)
+    G = g.reshape(39, n).copy()
+    x = np.arange(n) % nx
+    slab = (x >= 2) & (x <= 9)
+    e_now = (F * q[:, None]).sum(0) + G.sum(0)
+    G[:, slab] += ((1.0 * 0.01 + 5.0 * 0.1 - e_now[slab]) / 39.0)[None, :]
+    o.set_state(f, G.reshape(-1), lam)
+    o.step(1)
+    s = lbm.Solver(shape, storage="fp64", tau=0.6, newton_tol=1e-13)
+    s.set_state(f, G.reshape(-1), lam)
+    st, code = lbm.lbm_step(s.ctx, 1, with_stats=True)
+    assert code == lbm.LBM_E_NEWTON
+    assert st.failed == o.stats.failed > 0
+    assert list(st.alpha_hist) == list(o.stats.alpha_hist)
+    f1, g1, lam1 = s.get_state()
+    assert max_rel(f1, o.f) <= TOL and max_rel(g1, o.g) <= TOL
+    assert np.max(np.abs(lam1 - o.lam)) <= 1e-9 * np.max(np.abs(o.lam))
     s.close()
 
 

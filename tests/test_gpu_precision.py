@@ -100,3 +100,29 @@ def test_mass_conservation_reduced_precision(lbm, storage):
     bound = 2e-6 if storage == "fp32s" else 2e-5
     assert drift < bound and edrift < bound
     s.close()
+
+
+@pytest.mark.parametrize("storage", ["fp32s", "fp16s"])
+def test_cells_without_equilibrium_keep_their_state(orc, lbm, storage):
+    """Uniform periodic state with no 13-moment equilibrium (T = 0.1 at
+    u = 0.1, forced through g): every cell fails, is not collided, and the
+    stored state and multipliers come back unchanged, bit for bit."""
+    shape = (8, 4, 4)
+    n = int(np.prod(shape))
+    rho, u, T = inputs.uniform_fields(n, 1.0, [0.1, 0.0, 0.0], 0.5)
+    o = orc.Oracle(*shape, gamma=1.4, tau=0.6, newton_tol=1e-13)
+    o.init(rho, u, T)
+    f, g, lam = o.f.copy(), o.g.copy(), o.lam.copy()
+    c = orc.velocities()
+    q = (c ** 2).sum(1)
+    F = f.reshape(39, n)
+    G = g.reshape(39, n)
+    G += ((1.0 * 0.01 + 5.0 * 0.1 - ((F * q[:, None]).sum(0) + G.sum(0))) / 39.0)[None, :]
+    s = lbm.Solver(shape, storage=storage, tau=0.6)
+    s.set_state(f, G.reshape(-1), lam)
+    f0, g0, l0 = s.get_state()
+    st, code = lbm.lbm_step(s.ctx, 2, with_stats=True)
+    assert code == lbm.LBM_E_NEWTON and st.failed == 2 * n and sum(st.alpha_hist) == 0
+    f1, g1, l1 = s.get_state()
+    assert np.array_equal(f0, f1) and np.array_equal(g0, g1) and np.array_equal(l0, l1)
+    s.close()

@@ -413,3 +413,48 @@ def test_uniform_stream_through_open_faces_is_steady(orc):
     m, _ = o.moments()
     np.testing.assert_allclose(m, m0, rtol=1e-12, atol=1e-12)
     assert o.stats.failed == 0
+
+
+def test_cell_without_equilibrium_is_not_collided(orc):
+    """Where the gathered moments have no 13-moment equilibrium the cell only
+    streams: its outputs are its gathered populations (checked against the
+    separate pure-streaming routine), its multipliers are kept, it counts as
+    failed and in no alpha branch; every other cell collides as usual, and the
+    domain totals stay conserved."""
+    shape = (16, 4, 4)
+    nx = shape[0]
+    n = int(np.prod(shape))
+    rho, u, T = inputs.uniform_fields(n, 1.0, [0.1, 0.0, 0.0], 0.5)
+    o = orc.Oracle(*shape, gamma=1.4, tau=0.6, newton_tol=1e-13)
+    o.init(rho, u, T)
+    f, g, lam = o.f.copy(), o.g.copy(), o.lam.copy()
+    # a slab x in [2, 9] made cold (T = 0.1 at u = 0.1, no equilibrium) through g
+    c = orc.velocities()
+    q = (c ** 2).sum(1)
+    F = f.reshape(39, n)
+    G = g.reshape(39, n).copy()
+    x = np.arange(n) % nx
+    slab = (x >= 2) & (x <= 9)
+    e_now = (F * q[:, None]).sum(0) + G.sum(0)
+    e_cold = 1.0 * 0.01 + 5.0 * 0.1
+    G[:, slab] += ((e_cold - e_now[slab]) / 39.0)[None, :]
+    o.set_state(f, G.reshape(-1), lam)
+    _, t0 = o.moments()
+    iters, eps = o.step(1, diagnostics=True)
+    failed = np.isnan(eps)
+    # the slab's middle (gathers only from the slab) cannot have an equilibrium
+    assert failed[(x == 6)].all() and failed[(x == 5)].all()
+    assert not failed[(x == 13)].any()
+    assert o.stats.failed == failed.sum()
+    assert sum(o.stats.alpha_hist) == n - failed.sum()
+    fs = orc.Oracle(*shape, gamma=1.4, tau=0.6).stream_only(f).reshape(39, n)
+    gs = orc.Oracle(*shape, gamma=1.4, tau=0.6).stream_only(G.reshape(-1)).reshape(39, n)
+    np.testing.assert_array_equal(o.f.reshape(39, n)[:, failed], fs[:, failed])
+    np.testing.assert_array_equal(o.g.reshape(39, n)[:, failed], gs[:, failed])
+    np.testing.assert_array_equal(o.lam.reshape(13, n)[:, failed], lam.reshape(13, n)[:, failed])
+    assert np.all(iters[failed] == o.p.newton_maxit)
+    # the collided cells differ from their gathered values
+    assert np.max(np.abs(o.f.reshape(39, n)[:, ~failed] - fs[:, ~failed])) > 1e-6
+    _, t1 = o.moments()
+    assert abs(t1[0] - t0[0]) <= 1e-13 * t0[0]
+    assert abs(t1[4] - t0[4]) <= 1e-12 * t0[4]
