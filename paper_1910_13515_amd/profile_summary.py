@@ -1,0 +1,167 @@
+"""Summarise rocprofv3 runs of bench.py into the committed profile files.
+
+Reads, under one output root:
+
+    trace/        rocprofv3 --kernel-trace --stats of bench.py (all three storage modes)
+    pmc_FETCH_SIZE/, pmc_WRITE_SIZE/          one counter per run, same bench command
+    pmc_FETCH_SIZE_copy/, pmc_WRITE_SIZE_copy/ the same counters over bench.py --copy-probe
+
+and writes ``profiles/step_kernel_tgv128.md`` (durations, counter bytes,
+calibration, the commands) and ``profiles/traffic.json`` (HBM bytes per step
+launch per mode, tied to a hash of the device sources), which bench.py reads
+for roofline.traffic.
+
+The counters are scaled by what they read for a plain device copy of known
+size (five copies of 1 GiB).
+
+    python -m paper_1910_13515_amd.profile_summary <root> [--commands file]
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PROFILES = os.path.join(ROOT, "profiles")
+
+# kernel-name fragment -> storage mode
+STEP_KERNELS = {"fp64": "step_kernel<double>", "fp32s": "step_kernel_f32", "fp16s": "step_kernelIDF16_"}
+ALT_NAMES = {"fp16s": "step_kernel<_Float16>", "fp64": "step_kernelIdE", "fp32s": "step_kernel_f32"}
+BYTES_PER_CELL = {"fp64": 2 * 78 * 8 + 2 * 13 * 8, "fp32s": 2 * 78 * 4 + 2 * 13 * 4, "fp16s": 2 * 78 * 2 + 2 * 13 * 4}
+CELLS = 128 ** 3
+COPY_BYTES = 1 << 30
+COPY_REPS = 5
+
+
+def _mode_of(name: str):
+    for m in STEP_KERNELS:
+        if STEP_KERNELS[m] in name or ALT_NAMES[m] in name:
+            return m
+    return None
+
+
+def _one(root, pattern):
+    hits = sorted(glob.glob(os.path.join(root, pattern), recursive=True))
+    if not hits:
+        raise FileNotFoundError(os.path.join(root, pattern))
+    return hits[0]
+
+
+def kernel_stats(root):
+    out = {}
+    with open(_one(root, "trace/**/tgv128_kernel_stats.csv")) as fh:
+        for row in csv.DictReader(fh):
+            m = _mode_of(row["Name"])
+            if m:
+                out[m] = {"kernel": row["Name"], "calls": int(row["Calls"]), "avg_ns": float(row["AverageNs"]),
+                          "min_ns": float(row["MinNs"]), "max_ns": float(row["MaxNs"])}
+    return out
+
+
+def counter_per_dispatch(root, sub, counter, select):
+    """Mean counter value (KiB) over the dispatches whose kernel name select() maps to a key."""
+    sums, counts = {}, {}
+    with open(_one(root, f"{sub}/**/tgv128_counter_collection.csv")) as fh:
+        for row in csv.DictReader(fh):
+            if row["Counter_Name"] != counter:
+                continue
+            key = select(row["Kernel_Name"])
+            if key is None:
+                continue
+            sums[key] = sums.get(key, 0.0) + float(row["Counter_Value"])
+            counts[key] = counts.get(key, 0) + 1
+    return {k: (sums[k] / counts[k], counts[k]) for k in sums}
+
+
+def _copy_select(name):
+    return "copy" if "copyBuffer" in name else None
+
+
+def counter_total(root, sub, counter, select):
+    """Sum of a counter (KiB) over the dispatches select() maps to a key."""
+    tot = {}
+    with open(_one(root, f"{sub}/**/copy_counter_collection.csv")) as fh:
+        for row in csv.DictReader(fh):
+            if row["Counter_Name"] == counter and select(row["Kernel_Name"]) is not None:
+                k = select(row["Kernel_Name"])
+                tot[k] = tot.get(k, 0.0) + float(row["Counter_Value"])
+    return tot
+
+
+def summarize(root, commands=None):
+    sys.path.insert(0, ROOT)
+    import bench  # the hash of the device sources the profile belongs to
+
+    ks = kernel_stats(root)
+    fetch = counter_per_dispatch(root, "pmc_FETCH_SIZE", "FETCH_SIZE", _mode_of)
+    write = counter_per_dispatch(root, "pmc_WRITE_SIZE", "WRITE_SIZE", _mode_of)
+    # bench.py --copy-probe: COPY_REPS device copies of 1 GiB (one or more
+    # copy dispatches each); calibrate on the totals
+    cf = counter_total(root, "pmc_FETCH_SIZE_copy", "FETCH_SIZE", _copy_select)["copy"]
+    cw = counter_total(root, "pmc_WRITE_SIZE_copy", "WRITE_SIZE", _copy_select)["copy"]
+    f_cal = COPY_REPS * COPY_BYTES / (cf * 1024.0)
+    w_cal = COPY_REPS * COPY_BYTES / (cw * 1024.0)
+    modes = {}
+    for m in ("fp64", "fp32s", "fp16s"):
+        if m not in ks or m not in fetch or m not in write:
+            continue
+        fb = fetch[m][0] * 1024.0 * f_cal
+        wb = write[m][0] * 1024.0 * w_cal
+        alg = BYTES_PER_CELL[m] * CELLS
+        avg_s = ks[m]["avg_ns"] * 1e-9
+        modes[m] = {
+            "kernel": ks[m]["kernel"], "calls": ks[m]["calls"], "avg_ns": ks[m]["avg_ns"],
+            "glups_from_avg": CELLS / avg_s / 1e9,
+            "algorithmic_bytes_per_launch": alg, "algorithmic_GBps": alg / avg_s / 1e9,
+            "fetch_kib_raw": fetch[m][0], "write_kib_raw": write[m][0], "dispatches_counted": fetch[m][1],
+            "hbm_read_bytes": fb, "hbm_write_bytes": wb, "hbm_bytes_per_launch": fb + wb,
+            "hbm_GBps": (fb + wb) / avg_s / 1e9, "traffic_over_algorithmic": (fb + wb) / alg,
+        }
+    data = {"kernel_hash": bench.kernel_hash(), "workload": "periodic 128^3 Taylor-Green vortex, Ma 0.5, Re 1600",
+            "cells_per_launch": CELLS,
+            "calibration": {"copy_bytes_each_way": COPY_BYTES, "copies": COPY_REPS,
+                            "fetch_kib_per_copy": cf / COPY_REPS, "write_kib_per_copy": cw / COPY_REPS,
+                            "fetch_factor": f_cal, "write_factor": w_cal},
+            "modes": modes}
+    os.makedirs(PROFILES, exist_ok=True)
+    with open(os.path.join(PROFILES, "traffic.json"), "w") as fh:
+        json.dump(data, fh, indent=1)
+    lines = ["# Fused step kernel, periodic 128^3 Taylor-Green vortex (Ma 0.5, Re 1600)", "",
+             f"Device sources hash (bench.kernel_hash): `{data['kernel_hash']}`", "",
+             "Per launch = one time step over all 2,097,152 cells, f and g.  Algorithmic bytes: 78 populations "
+             "read and written plus 13 multipliers read and written per cell (FP64 1456 B, FP32-shifted 728 B, "
+             "FP16-shifted 416 B).  HBM peak 8000 GB/s.", "",
+             "| storage | kernel | calls | avg us | GLUPS (avg) | algorithmic GB/s | frac of 8 TB/s | "
+             "FETCH KiB raw | WRITE KiB raw | HBM bytes/launch (calibrated) | HBM GB/s | traffic / algorithmic |",
+             "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for m, v in modes.items():
+        lines.append(f"| {m} | `{v['kernel']}` | {v['calls']} | {v['avg_ns'] / 1e3:.1f} | {v['glups_from_avg']:.3f} | "
+                     f"{v['algorithmic_GBps']:.0f} | {v['algorithmic_GBps'] / 8000:.3f} | {v['fetch_kib_raw']:.0f} | "
+                     f"{v['write_kib_raw']:.0f} | {v['hbm_bytes_per_launch']:.4g} | {v['hbm_GBps']:.0f} | "
+                     f"{v['traffic_over_algorithmic']:.3f} |")
+    c = data["calibration"]
+    lines += ["", "Counter calibration (plain device copy of 1 GiB, `bench.py --copy-probe`): "
+              f"FETCH_SIZE reads {c['fetch_kib_per_copy']:.0f} KiB per copy dispatch (factor {c['fetch_factor']:.3f}), "
+              f"WRITE_SIZE {c['write_kib_per_copy']:.0f} KiB (factor {c['write_factor']:.3f}).", ""]
+    if commands:
+        lines += ["Commands (run from the repository root on the GPU host, `cd /tmp && export TMPDIR=/tmp` first "
+                  "for the profiler):", "", "```"] + [ln.rstrip() for ln in open(commands) if ln.strip()] + ["```", ""]
+    with open(os.path.join(PROFILES, "step_kernel_tgv128.md"), "w") as fh:
+        fh.write("\n".join(lines))
+    return data
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("root")
+    ap.add_argument("--commands", default=None)
+    args = ap.parse_args()
+    print(json.dumps(summarize(args.root, args.commands), indent=1))
+
+
+if __name__ == "__main__":
+    main()
