@@ -218,7 +218,8 @@ __device__ __forceinline__ int solve_multipliers(const C u[3], C T, C lam[kM], C
     C t = C(0);
     C n0 = C(0);
     int it = 0, ls = 0, cap = maxit;
-    bool fresh = true, cold = false;
+    bool fresh = true, cold = false, floor_stop = false;
+    bool near = false;  // the last accepted iterate is within 8 times the bound
     int status = kFailed;
     for (;;) {
         eval_exponentials(lam, f0, fp, fm);
@@ -234,7 +235,11 @@ __device__ __forceinline__ int solve_multipliers(const C u[3], C T, C lam[kM], C
 #pragma unroll
         for (int k = 0; k < kM; ++k) n2 += G[k] * G[k];
         n2 = dsqrt(n2);
-        if (!fresh && !(n2 < n0) && ls < 39) {
+        // the full step does not lower the residual while the accepted
+        // iterate is within 8 times the bound: the residual sits at the
+        // round-off floor; the step is taken and the solve stops
+        floor_stop = !fresh && !(n2 < n0) && ls == 0 && near;
+        if (!fresh && !(n2 < n0) && ls < 39 && !floor_stop) {
             t *= C(0.5);
             ++ls;
 #pragma unroll
@@ -256,7 +261,8 @@ __device__ __forceinline__ int solve_multipliers(const C u[3], C T, C lam[kM], C
         resid[2] = G[2];
         resid[3] = G[3];
         resid[4] = G[4] + G[5] + G[6];
-        if (r <= bound) {
+        near = r <= C(8) * bound;
+        if (r <= bound || floor_stop) {
             status = cold ? kConvergedCold : kConverged;
             break;
         }

@@ -312,3 +312,61 @@ def test_tau_from_reynolds_uses_model_viscosity(orc, lbm):
     assert abs(info.tau - orc.tau_from_reynolds(U, 20.0, 1600.0, 0.5)) < 1e-9
     np.testing.assert_allclose(list(info.u_ref), [U, 0, 0], rtol=1e-15)
     s.close()
+
+
+def test_full_size_tgv128_step(orc, lbm):
+    """The benchmark's workload at its full size (periodic 128^3 TGV, Ma 0.5,
+    Re 1600), in the launch configuration the benchmark times: two GPU steps
+    from the analytic initial state against two oracle steps, every cell."""
+    n = 128
+    gamma, T0, ma = 1.4, 0.5, 0.5
+    U = ma * np.sqrt(gamma * T0)
+    fields = inputs.taylor_green_fields(n, U, T0)
+    kw = dict(gamma=gamma, mach=ma, reynolds=1600.0, length_ref=n / (2 * np.pi), T_ref=T0, u_dir=(1, 0, 0),
+              kn_relax=True, newton_tol=1e-13, newton_maxit=30)
+    s = lbm.Solver((n, n, n), fields=fields, storage="fp64", **kw)
+    tau = s.info().tau
+    _log(f"tgv128 tau={tau:.6f}")
+    o = orc.Oracle(n, n, n, gamma=gamma, tau=tau, kn_relax=True, newton_tol=1e-13, newton_maxit=30)
+    assert o.init(*fields) == 0
+    o.step(2)
+    st, code = lbm.lbm_step(s.ctx, 2, with_stats=True)
+    assert code == lbm.LBM_OK and st.failed == 0
+    m, t = s.moments()
+    mo, to = o.moments()
+    em = moment_error(m, mo)
+    f, g, lam = s.get_state()
+    ef, eg = max_rel(f, o.f), max_rel(g, o.g)
+    _log(f"tgv128: moments {em}, populations f {ef:.2e} g {eg:.2e}")
+    assert max(em) <= TOL and ef <= TOL and eg <= TOL
+    assert np.all(np.abs(t - to) <= 1e-12 * np.abs(to).max())
+    s.close()
+
+
+def test_full_size_airfoil_step(orc, lbm):
+    """The supersonic airfoil at its full size (2048 x 1024, NACA0012 of chord
+    256, Ma 1.5, Re 1e4, equilibrium faces, bounce-back): three GPU steps from
+    the free stream against the oracle, every cell."""
+    from paper_1910_13515_amd import precision_study as ps
+    shape, solid, kw = ps.airfoil_case(1.0)
+    kw = dict(kw, newton_tol=1e-13, newton_maxit=30)
+    s = lbm.Solver(shape, solid=solid, storage="fp64", **kw)
+    info = s.info()
+    _log(f"airfoil tau={info.tau:.6f} fluid={info.fluid_cells}")
+    o = orc.Oracle(*shape, gamma=kw["gamma"], tau=info.tau, kn_relax=True, faces=kw["faces"], solid=solid,
+                   newton_tol=1e-13, newton_maxit=30)
+    n = int(np.prod(shape))
+    u = np.zeros((3, n))
+    u[0] = info.u_ref[0]
+    assert o.init(np.ones(n), u, np.full(n, kw["T_ref"])) == 0
+    o.step(3)
+    st, code = lbm.lbm_step(s.ctx, 3, with_stats=True)
+    assert code == lbm.LBM_OK and st.failed == 0
+    m, _ = s.moments()
+    mo, _ = o.moments()
+    em = moment_error(m, mo)
+    f, g, _ = s.get_state()
+    ef, eg = max_rel(f, o.f), max_rel(g, o.g)
+    _log(f"airfoil: moments {em}, populations f {ef:.2e} g {eg:.2e}")
+    assert max(em) <= TOL and ef <= TOL and eg <= TOL
+    s.close()

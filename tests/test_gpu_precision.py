@@ -18,7 +18,9 @@ from paper_1910_13515_amd import inputs  # noqa: E402
 
 # bars per storage mode: (single-step populations rel. to max, single-step
 # moments, Sod plateau L1 of rho relative to the FP64 run)
-BARS = {"fp32s": (1e-5, 3e-5, 2e-4), "fp16s": (3e-4, 1e-3, 5e-3)}
+# FP16: a stored deviation is rounded to 11 bits of its shell-scaled value,
+# which reaches about twice the shell scale: up to 2^-11 * 2 ~ 1e-3 of it.
+BARS = {"fp32s": (1e-5, 3e-5, 2e-4), "fp16s": (1e-3, 1e-3, 5e-3)}
 
 
 @pytest.fixture(scope="module")
@@ -125,4 +127,55 @@ def test_cells_without_equilibrium_keep_their_state(orc, lbm, storage):
     assert code == lbm.LBM_E_NEWTON and st.failed == 2 * n and sum(st.alpha_hist) == 0
     f1, g1, l1 = s.get_state()
     assert np.array_equal(f0, f1) and np.array_equal(g0, g1) and np.array_equal(l0, l1)
+    s.close()
+
+
+@pytest.mark.parametrize("storage", ["fp32s", "fp16s"])
+def test_full_size_tgv128_step(orc, lbm, storage):
+    """The benchmark's workload at full size (128^3 TGV): one reduced-precision
+    GPU step from the oracle's state after one step, against the oracle's
+    second step, every cell, at the single-step bars."""
+    n = 128
+    gamma, T0, ma = 1.4, 0.5, 0.5
+    U = ma * np.sqrt(gamma * T0)
+    fields = inputs.taylor_green_fields(n, U, T0)
+    kw = dict(gamma=gamma, mach=ma, reynolds=1600.0, length_ref=n / (2 * np.pi), T_ref=T0, u_dir=(1, 0, 0),
+              kn_relax=True)
+    s = lbm.Solver((n, n, n), fields=fields, storage=storage, **kw)
+    tau = s.info().tau
+    o = orc.Oracle(n, n, n, gamma=gamma, tau=tau, kn_relax=True, newton_tol=1e-13, newton_maxit=30)
+    assert o.init(*fields) == 0
+    o.step(1)
+    s.set_state(o.f, o.g, o.lam)
+    _, eps = o.step(1, diagnostics=True)
+    st = s.step(1, stats=True)
+    m, _ = s.moments()
+    mo, _ = o.moments()
+    em = moment_error(m, mo)
+    fg, gg, _ = s.get_state()
+    # the branch of alpha(eps) is decided by a comparison of eps with 0.01,
+    # 0.1 and 1; where the FP64 eps lies within 0.2% of a threshold the
+    # reduced-precision eps may fall on the other side, and the relaxation
+    # time of that cell differs by the branch ratio: those cells are held to
+    # the bound of a branch change instead
+    thr = np.array([1e-2, 1e-1, 1.0])
+    near = np.min(np.abs(eps[:, None] - thr[None, :]) / thr[None, :], axis=1) < 2e-3
+    N = n ** 3
+    F, G = fg.reshape(39, N), gg.reshape(39, N)
+    Fo, Go = o.f.reshape(39, N), o.g.reshape(39, N)
+    scale_f, scale_g = np.abs(Fo).max(), np.abs(Go).max()
+    ef = np.abs(F[:, ~near] - Fo[:, ~near]).max() / scale_f
+    eg = np.abs(G[:, ~near] - Go[:, ~near]).max() / scale_g
+    ef_near = np.abs(F[:, near] - Fo[:, near]).max() / scale_f if near.any() else 0.0
+    eg_near = np.abs(G[:, near] - Go[:, near]).max() / scale_g if near.any() else 0.0
+    _log(f"{storage} tgv128: populations f {ef:.2e} g {eg:.2e} ({near.sum()} cells near an alpha threshold: "
+         f"f {ef_near:.2e} g {eg_near:.2e}); moments {em}")
+    bar_pop, bar_mom, _ = BARS[storage]
+    assert st.failed == 0
+    assert near.sum() < 1e-2 * N
+    assert ef < bar_pop and eg < bar_pop
+    # a branch change moves omega by at most 1/tau - 1/(1.35 tau) (< 0.6 here)
+    # times |f - f^eq| (a few per cent of f at these eps): 1e-2 of the scale
+    assert ef_near < 1e-2 and eg_near < 1e-2
+    assert max(em) < bar_mom
     s.close()
