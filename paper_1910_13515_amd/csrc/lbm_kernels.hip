@@ -25,6 +25,9 @@
 #ifndef LBM_FP32_DMA
 #define LBM_FP32_DMA 1
 #endif
+#ifndef LBM_FP64_DMA
+#define LBM_FP64_DMA 1
+#endif
 
 namespace lbm13 {
 
@@ -644,7 +647,10 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f32(const SlotTa
             for (int i0 = 0; i0 < 2 * kQ; i0 += 4) {
                 if (i0 + r < 2 * kQ) {
                     const f32::v4f v = *reinterpret_cast<const f32::v4f *>(lcol + i0 * kBlockThreads);
-                    *reinterpret_cast<f32::v4f __attribute__((address_space(1))) *>(dstb + (uint64_t)i0 * nS64 + voff) = v;
+                    // streaming store: the next step reads these rows long after
+                    // the caches have turned over
+                    __builtin_nontemporal_store(
+                        v, reinterpret_cast<f32::v4f __attribute__((address_space(1))) *>(dstb + (uint64_t)i0 * nS64 + voff));
                 }
             }
         } else if (in_grid) {
@@ -653,6 +659,275 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f32(const SlotTa
         }
     }
     if (stats) {
+        int64_t red[kStatWords];
+#pragma unroll
+        for (int k = 0; k < kStatWords; ++k) red[k] = (k == 1) ? wave_max(acc[k]) : wave_sum(acc[k]);
+        if (lane == 0) {
+            int64_t *p = stats + ((int64_t)blockIdx.x * kWavesPerBlock + wave) * kStatWords;
+#pragma unroll
+            for (int k = 0; k < kStatWords; ++k) p[k] = (k == 1) ? (red[k] > p[k] ? red[k] : p[k]) : p[k] + red[k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 step with the same structure as the FP32 one: the gather goes global ->
+// LDS directly, each double as two dword transfers (low words of the 64 cells
+// of a row, then high words), so that no register holds a gathered value and
+// every transfer of the wave is in flight at once.  LDS row i of wave w: 64
+// low words at i*512 + w*128, 64 high words 64 words further; results go
+// back to the same places, and full rows leave as 16-byte-per-lane stores of
+// two cells.  One wave per SIMD (the FP64 solve needs the register file).
+namespace f64 {
+
+using lds_u32 = uint32_t __attribute__((address_space(3)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+constexpr int kRowWords = 2 * kBlockThreads;  // words per LDS row of the block
+
+// a uniform plane base forced into SGPRs where it is used: the access is
+// then base + 32-bit lane offset, and no per-lane 64-bit address stays live
+__device__ __forceinline__ gbyte *splane(gbyte *p)
+{
+    __asm__ volatile("" : "+s"(p));
+    return p;
+}
+
+struct Park {
+    lds_u32 *base;  // lane's low word of row 0
+    __device__ __forceinline__ double get(int i) const
+    {
+        const uint32_t lo = base[i * kRowWords], hi = base[i * kRowWords + kSegment];
+        return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));
+    }
+    __device__ __forceinline__ void put(int i, double v) const
+    {
+        const uint64_t b = __builtin_bit_cast(uint64_t, v);
+        base[i * kRowWords] = (uint32_t)b;
+        base[i * kRowWords + kSegment] = (uint32_t)(b >> 32);
+    }
+};
+
+// the two dword transfers of one double per lane into LDS row `row`
+__device__ __forceinline__ void dma8(gcbyte *gaddr, lds_u32 *row)
+{
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)gaddr,
+                                     (void __attribute__((address_space(3))) *)row, 4, 0, 0);
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(gaddr + 4),
+                                     (void __attribute__((address_space(3))) *)(row + kSegment), 4, 0, 0);
+}
+
+// gather of one cell's 78 values (rows: the wave's low words of row 0);
+// copy = the cell's own values
+__device__ __forceinline__ void gather(const SlotDesc &d, gcbyte *srcb, int x, int y, int z, uint32_t cell,
+                                       uint64_t links, bool copy, lds_u32 *rows)
+{
+    const uint64_t nS64 = (uint64_t)d.n * 8;
+    const uint32_t nS = (uint32_t)nS64;
+    const uint32_t cellS = cell * 8u;
+    const uint32_t nx = (uint32_t)d.nx, nxy = (uint32_t)d.nx * (uint32_t)d.ny;
+    uint32_t Xo[7], Yo[7], Zo[7];
+#pragma unroll
+    for (int c = -3; c <= 3; ++c) {
+        Xo[c + 3] = (uint32_t)source_coord(x, c, d.nx, d.axis[0] == kAxisPeriodic, d.neumann_lo[0], d.neumann_hi[0]) * 8u;
+        Yo[c + 3] = (uint32_t)source_coord(y, c, d.ny, d.axis[1] == kAxisPeriodic, d.neumann_lo[1], d.neumann_hi[1]) * nx * 8u;
+        Zo[c + 3] = (uint32_t)source_coord(z, c, d.nz, d.axis[2] == kAxisPeriodic, d.neumann_lo[2], d.neumann_hi[2]) * nxy * 8u;
+    }
+    dma8(srcb + cellS, rows);
+    dma8(srcb + (uint64_t)kQ * nS64 + cellS, rows + kQ * kRowWords);
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p) {
+        const int a = 2 * p + 1, b = 2 * p + 2;
+        const int cx = kPairVel[p][0], cy = kPairVel[p][1], cz = kPairVel[p][2];
+        uint32_t oa = Xo[cx + 3] + (Yo[cy + 3] + Zo[cz + 3]);
+        uint32_t ob = nS + (Xo[3 - cx] + (Yo[3 - cy] + Zo[3 - cz]));
+        oa = ((links >> a) & 1ull) ? nS + cellS : oa;
+        ob = ((links >> b) & 1ull) ? cellS : ob;
+        oa = copy ? cellS : oa;
+        ob = copy ? nS + cellS : ob;
+        gcbyte *bf = srcb + (uint64_t)a * nS64;
+        gcbyte *bg = srcb + (uint64_t)(kQ + a) * nS64;
+        dma8(bf + oa, rows + a * kRowWords);
+        dma8(bf + ob, rows + b * kRowWords);
+        dma8(bg + oa, rows + (kQ + a) * kRowWords);
+        dma8(bg + ob, rows + (kQ + b) * kRowWords);
+    }
+}
+
+// moments, Newton, sensor and relaxation of one fluid cell whose gathered
+// values sit in LDS; the results replace them
+template <bool kStats>
+__device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const Park &pk, int32_t (&acc)[kStatWords])
+{
+    using C = double;
+    C rho = C(-0.0), j0 = C(-0.0), j1 = C(-0.0), j2 = C(-0.0), e = C(-0.0);
+    C sg = pk.get(kQ);
+    rho += pk.get(0);
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p) {
+        const C fa = pk.get(2 * p + 1), fb = pk.get(2 * p + 2);
+        const C sp = fa + fb, ap = fa - fb;
+        rho += sp;
+        j0 += C(kPairVel[p][0]) * ap;
+        j1 += C(kPairVel[p][1]) * ap;
+        j2 += C(kPairVel[p][2]) * ap;
+        e += C(pair_q(p)) * sp;
+        sg += pk.get(kQ + 2 * p + 1) + pk.get(kQ + 2 * p + 2);
+        // read the rows a few pairs at a time, not all at once
+        if ((p & 1) == 1) __asm__ volatile("" ::: "memory");
+    }
+    e += sg;
+    // the gathered values are read again after the solve, not kept in registers
+    __asm__ volatile("" ::: "memory");
+    C u[3];
+    u[0] = j0 / rho;
+    u[1] = j1 / rho;
+    u[2] = j2 / rho;
+    const C T = (e - rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2])) / (C(d.two_cv) * rho);
+
+    gbyte *lamb = (gbyte *)d.lam;
+    const uint64_t nL64 = (uint64_t)d.n * 8;
+    const uint32_t cellL = cell * 8u;
+    C lam[kM];
+#pragma unroll
+    for (int k = 0; k < kM; ++k) lam[k] = gload<C>(splane(lamb + (uint64_t)k * nL64), cellL);
+
+    C f0, fp[kPairs], fm[kPairs];
+    int iters = 0;
+    C resid[5];
+    const int status = solve_multipliers<C>(u, T, lam, f0, fp, fm, C(d.tol), d.maxit, d.maxit_cold, iters, resid);
+
+    // Knudsen sensor over f (Eq. eq:DeltaAvg) and relaxation branch (Eq. eq:alpha)
+    C eps = C(0);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const C e_i = (i == 0) ? f0 : (((i - 1) & 1) == 0 ? fp[(i - 1) >> 1] : fm[(i - 1) >> 1]);
+        const C feq = rho * e_i;
+        eps += fabs(pk.get(i) - feq) * recip(feq);
+    }
+    eps *= C(1.0 / kQ);
+    int br = 0;
+    if (d.kn_relax) br = (eps < C(1e-2)) ? 0 : (eps < C(1e-1)) ? 1 : (eps < C(1)) ? 2 : 3;
+    // a cell whose multipliers were not found is not collided (omega = 0
+    // against the finite values the solver leaves): gathered values stored
+    // unchanged, multipliers kept for the next warm start
+    const bool failed = status == kFailed;
+    C omega = d.omega[0];
+    omega = br == 1 ? d.omega[1] : omega;
+    omega = br == 2 ? d.omega[2] : omega;
+    omega = br == 3 ? d.omega[3] : omega;
+    omega = failed ? C(0) : omega;
+    const C dT = C(d.delta) * T;
+    __asm__ volatile("" ::: "memory");
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const C e_i = (i == 0) ? f0 : (((i - 1) & 1) == 0 ? fp[(i - 1) >> 1] : fm[(i - 1) >> 1]);
+        const C feq = rho * e_i;
+        const C geq = dT * feq;
+        const C hf = pk.get(i), hg = pk.get(kQ + i);
+        pk.put(i, hf + omega * (feq - hf));
+        pk.put(kQ + i, hg + omega * (geq - hg));
+    }
+    if (!failed) {
+#pragma unroll
+        for (int k = 0; k < kM; ++k) gstore<C>(splane(lamb + (uint64_t)k * nL64), cellL, lam[k]);
+    }
+
+    if constexpr (kStats) {
+        acc[0] += iters;
+        acc[1] = iters > acc[1] ? iters : acc[1];
+        acc[2] += failed;
+        acc[3] += status == kConvergedCold;
+        acc[4] += !failed && br == 0;
+        acc[5] += !failed && br == 1;
+        acc[6] += !failed && br == 2;
+        acc[7] += !failed && br == 3;
+    }
+}
+
+}  // namespace f64
+
+// kStats: per-wave statistics (iterations, failures, alpha branches) into
+// stats; the variant without them keeps those registers free for the solve
+template <bool kStats>
+__global__ __launch_bounds__(kBlockThreads, 1) void step_kernel_f64(const SlotTable *__restrict__ tab, int j,
+                                                                   int64_t *__restrict__ stats)
+{
+    __shared__ uint32_t park[2 * kQ * f64::kRowWords];
+    int32_t acc[kStatWords] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int total = tab->total_blocks;
+    const int xcd = blockIdx.x & 7;
+    const int per_xcd = gridDim.x >> 3;
+    const int lo = (int)(((int64_t)total * xcd) >> 3);
+    const int hi = (int)(((int64_t)total * (xcd + 1)) >> 3);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    f64::lds_u32 *const rows0 = (f64::lds_u32 *)park + wave * (2 * kSegment);
+    for (int b = lo + (int)(blockIdx.x >> 3); b < hi; b += per_xcd) {
+        // the 156 row addresses are cheap to form; keep the compiler from
+        // hoisting them out of the loop into registers
+        f64::lds_u32 *rows = rows0;
+        __asm__ volatile("" : "+s"(rows));
+        const f64::Park pk{rows + lane};
+        const int s = find_slot(tab, b);
+        const SlotDesc &d = tab->slot[s];
+        if (j >= d.steps_todo) continue;
+        const int64_t seg = (int64_t)(b - tab->block_start[s]) * kWavesPerBlock + wave;
+        if (seg >= d.segments) continue;
+        const int segx = (int)(seg % d.nsegx);
+        const int row = (int)(seg / d.nsegx);
+        const int y = row % d.ny;
+        const int z = row / d.ny;
+        const int x = segx * kSegment + lane;
+        const uint32_t cell0 = (uint32_t)(segx * kSegment) + (uint32_t)d.nx * (uint32_t)row;
+        // 16-byte stores of two cells need an even first cell
+        const bool full = (segx * kSegment + kSegment <= d.nx) && (d.nx % 2 == 0);
+        const bool in_grid = x < d.nx;
+        const uint32_t cell = cell0 + (uint32_t)lane;
+        const int par = (d.parity0 + j) & 1;
+        gcbyte *srcb = (gcbyte *)d.buf[par];
+        gbyte *dstb = (gbyte *)d.buf[par ^ 1];
+        bool fluid = in_grid && is_fluid_coord(d, x, y, z);
+        uint64_t links = 0;
+        if (fluid && d.has_links) links = d.links[cell];
+        if (links >> 63) fluid = false;  // solid cells pass through unchanged
+        if (in_grid) f64::gather(d, srcb, x, y, z, cell, links, !fluid, rows);
+        f32::wait_vmem();
+        int32_t it_cell = 0;
+        if (fluid) {
+            const int32_t before = acc[0];
+            f64::collide<kStats>(d, cell, pk, acc);
+            it_cell = acc[0] - before;
+        }
+        if constexpr (kStats) {
+            const int32_t wmax = wave_max(it_cell);
+            acc[8] += lane == 0 ? wmax : 0;
+            acc[9] += lane == 0 ? 1 : 0;
+        }
+        // store the wave's rows
+        const uint64_t nS64 = (uint64_t)d.n * 8;
+        if (full) {
+            // lanes 32r..32r+31 store row i0 + r, two cells each
+            const int r = lane >> 5, c2 = (lane & 31) * 2;
+            uint32_t voff = (uint32_t)r * (uint32_t)nS64 + (cell0 + (uint32_t)c2) * 8u;
+            const f64::lds_u32 *lrow = rows + r * f64::kRowWords + c2;
+            __asm__ volatile("" : "+v"(voff));
+#pragma unroll
+            for (int i0 = 0; i0 < 2 * kQ; i0 += 2) {
+                const f64::v2u lw = *reinterpret_cast<const f64::v2u __attribute__((address_space(3))) *>(
+                    lrow + i0 * f64::kRowWords);
+                const f64::v2u hw = *reinterpret_cast<const f64::v2u __attribute__((address_space(3))) *>(
+                    lrow + i0 * f64::kRowWords + kSegment);
+                const f64::v4u v = {lw.x, hw.x, lw.y, hw.y};
+                __builtin_nontemporal_store(
+                    v, reinterpret_cast<f64::v4u __attribute__((address_space(1))) *>(dstb + (uint64_t)i0 * nS64 + voff));
+            }
+        } else if (in_grid) {
+#pragma unroll
+            for (int i = 0; i < 2 * kQ; ++i) gstore<double>(dstb + (uint64_t)i * nS64, cell * 8u, pk.get(i));
+        }
+    }
+    if constexpr (kStats) {
         int64_t red[kStatWords];
 #pragma unroll
         for (int k = 0; k < kStatWords; ++k) red[k] = (k == 1) ? wave_max(acc[k]) : wave_sum(acc[k]);
@@ -909,7 +1184,16 @@ static hipError_t launch_step_t(const SlotTable *tab, int grid, int j, int64_t *
 hipError_t launch_step(int storage, const SlotTable *tab, int grid, int j, int64_t *stats, hipStream_t st)
 {
     switch (storage) {
-    case kStoreF64: return launch_step_t<double>(tab, grid, j, stats, st);
+    case kStoreF64:
+#if LBM_FP64_DMA
+        if (stats)
+            hipLaunchKernelGGL(step_kernel_f64<true>, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
+        else
+            hipLaunchKernelGGL(step_kernel_f64<false>, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
+        return hipGetLastError();
+#else
+        return launch_step_t<double>(tab, grid, j, stats, st);
+#endif
     case kStoreF32:
 #if LBM_FP32_DMA
         hipLaunchKernelGGL(step_kernel_f32, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
@@ -924,7 +1208,11 @@ hipError_t launch_step(int storage, const SlotTable *tab, int grid, int j, int64
 const void *step_kernel_symbol(int storage)
 {
     switch (storage) {
+#if LBM_FP64_DMA
+    case kStoreF64: return reinterpret_cast<const void *>(&step_kernel_f64<false>);
+#else
     case kStoreF64: return reinterpret_cast<const void *>(&step_kernel<double>);
+#endif
 #if LBM_FP32_DMA
     case kStoreF32: return reinterpret_cast<const void *>(&step_kernel_f32);
 #else
