@@ -78,6 +78,8 @@ std::string validate(const lbm_params *p)
     if (2 * n * storage_bytes(p->storage) >= ((int64_t)1 << 32)) return "grid too large for this storage mode";
     // FP32: row stores address four population arrays from one base
     if (p->storage == LBM_STORE_FP32_SHIFTED && 4 * n * 4 >= ((int64_t)1 << 32)) return "grid too large for FP32 storage";
+    // the FP16 row stores reach 8 planes (of 2n bytes) from one 32-bit lane offset
+    if (p->storage == LBM_STORE_FP16_SHIFTED && 8 * n * 2 >= ((int64_t)1 << 32)) return "grid too large for FP16 storage";
     if (p->shift_ref < 0 || p->shift_ref > 1) return "shift_ref must be 0 or 1";
     const int dims[3] = {p->nx, p->ny, p->nz};
     for (int a = 0; a < 3; ++a) {

@@ -28,6 +28,9 @@
 #ifndef LBM_FP64_DMA
 #define LBM_FP64_DMA 1
 #endif
+#ifndef LBM_FP16_DMA
+#define LBM_FP16_DMA 1
+#endif
 
 namespace lbm13 {
 
@@ -230,8 +233,8 @@ __device__ __forceinline__ void relax_all(const SlotDesc &d, gbyte *dstb, uint64
     (relax_one<I, S, C>(d, dstb, nS64, cellS, rho, dT, omega, f0, fp, fm, pk), ...);
 }
 
-template <int I, class S, class C>
-__device__ __forceinline__ C eps_term(const SlotDesc &d, C rho, C f0, const C *fp, const C *fm, const Park<C> &pk)
+template <int I, class S, class C, class PK>
+__device__ __forceinline__ C eps_term(const SlotDesc &d, C rho, C f0, const C *fp, const C *fm, const PK &pk)
 {
     const C feq = rho * feq_of<I>(f0, fp, fm);
     const C hf = pk.get(I);
@@ -241,12 +244,12 @@ __device__ __forceinline__ C eps_term(const SlotDesc &d, C rho, C f0, const C *f
     return fabs(diff) * recip(feq);
 }
 
-template <class S, class C, int... I>
-__device__ __forceinline__ C eps_sum(const SlotDesc &d, C rho, C f0, const C *fp, const C *fm, const Park<C> &pk,
+template <class S, class C, class PK, int... I>
+__device__ __forceinline__ C eps_sum(const SlotDesc &d, C rho, C f0, const C *fp, const C *fm, const PK &pk,
                                      std::integer_sequence<int, I...>)
 {
     C e = C(-0.0);
-    ((e += eps_term<I, S, C>(d, rho, f0, fp, fm, pk)), ...);
+    ((e += eps_term<I, S, C, PK>(d, rho, f0, fp, fm, pk)), ...);
     return e;
 }
 
@@ -457,29 +460,47 @@ __device__ __forceinline__ void dma4(gcbyte *gaddr, lds_float *row_base)
                                      (void __attribute__((address_space(3))) *)row_base, 4, 0, 0);
 }
 
+// a 2-byte transfer lands zero-extended in the lane's dword of the LDS row
+__device__ __forceinline__ void dma2(gcbyte *gaddr, lds_float *row_base)
+{
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)gaddr,
+                                     (void __attribute__((address_space(3))) *)row_base, 2, 0, 0);
+}
+
+template <int kBytes>
+__device__ __forceinline__ void dma(gcbyte *gaddr, lds_float *row_base)
+{
+    if constexpr (kBytes == 4) dma4(gaddr, row_base);
+    else dma2(gaddr, row_base);
+}
+
 __device__ __forceinline__ float uniform(float v)
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
 }
 
-// gather of one cell's 78 values into the wave's LDS rows (row i at
-// rows + i*256); copy = the cell's own values
+// gather of one cell's 78 values (stored kBytes wide) into the wave's LDS
+// rows (row i at rows + i*256, one dword per lane); copy = the cell's own values
+template <int kBytes = 4>
 __device__ __forceinline__ void gather(const SlotDesc &d, gcbyte *srcb, int x, int y, int z, uint32_t cell,
                                        uint64_t links, bool copy, lds_float *rows)
 {
-    const uint64_t nS64 = (uint64_t)d.n * 4;
+    const uint64_t nS64 = (uint64_t)d.n * kBytes;
     const uint32_t nS = (uint32_t)nS64;
-    const uint32_t cellS = cell * 4u;
+    const uint32_t cellS = cell * (uint32_t)kBytes;
     const uint32_t nx = (uint32_t)d.nx, nxy = (uint32_t)d.nx * (uint32_t)d.ny;
     uint32_t Xo[7], Yo[7], Zo[7];
 #pragma unroll
     for (int c = -3; c <= 3; ++c) {
-        Xo[c + 3] = (uint32_t)source_coord(x, c, d.nx, d.axis[0] == kAxisPeriodic, d.neumann_lo[0], d.neumann_hi[0]) * 4u;
-        Yo[c + 3] = (uint32_t)source_coord(y, c, d.ny, d.axis[1] == kAxisPeriodic, d.neumann_lo[1], d.neumann_hi[1]) * nx * 4u;
-        Zo[c + 3] = (uint32_t)source_coord(z, c, d.nz, d.axis[2] == kAxisPeriodic, d.neumann_lo[2], d.neumann_hi[2]) * nxy * 4u;
+        Xo[c + 3] = (uint32_t)source_coord(x, c, d.nx, d.axis[0] == kAxisPeriodic, d.neumann_lo[0], d.neumann_hi[0]) *
+                    (uint32_t)kBytes;
+        Yo[c + 3] = (uint32_t)source_coord(y, c, d.ny, d.axis[1] == kAxisPeriodic, d.neumann_lo[1], d.neumann_hi[1]) *
+                    nx * (uint32_t)kBytes;
+        Zo[c + 3] = (uint32_t)source_coord(z, c, d.nz, d.axis[2] == kAxisPeriodic, d.neumann_lo[2], d.neumann_hi[2]) *
+                    nxy * (uint32_t)kBytes;
     }
-    dma4(srcb + cellS, rows);
-    dma4(srcb + (uint64_t)kQ * nS64 + cellS, rows + kQ * kBlockThreads);
+    dma<kBytes>(srcb + cellS, rows);
+    dma<kBytes>(srcb + (uint64_t)kQ * nS64 + cellS, rows + kQ * kBlockThreads);
 #pragma unroll
     for (int p = 0; p < kPairs; ++p) {
         const int a = 2 * p + 1, b = 2 * p + 2;
@@ -492,20 +513,39 @@ __device__ __forceinline__ void gather(const SlotDesc &d, gcbyte *srcb, int x, i
         ob = copy ? nS + cellS : ob;
         gcbyte *bf = srcb + (uint64_t)a * nS64;
         gcbyte *bg = srcb + (uint64_t)(kQ + a) * nS64;
-        dma4(bf + oa, rows + a * kBlockThreads);
-        dma4(bf + ob, rows + b * kBlockThreads);
-        dma4(bg + oa, rows + (kQ + a) * kBlockThreads);
-        dma4(bg + ob, rows + (kQ + b) * kBlockThreads);
+        dma<kBytes>(bf + oa, rows + a * kBlockThreads);
+        dma<kBytes>(bf + ob, rows + b * kBlockThreads);
+        dma<kBytes>(bg + oa, rows + (kQ + a) * kBlockThreads);
+        dma<kBytes>(bg + ob, rows + (kQ + b) * kBlockThreads);
     }
 }
 
+// FP16 storage seen through the FP32 park: a row word holds the stored half
+// (zero-extended); reads decode (times the shell scale), writes encode
+struct ParkHalf {
+    uint32_t *base;  // &lds_words[0][threadIdx.x]
+    const float *scale;      // shell scales of f (0..5) then g (6..11)
+    const float *inv_scale;
+    __device__ __forceinline__ float get(int i) const
+    {
+        const uint16_t h = (uint16_t)base[i * kBlockThreads];
+        const int k = (i < kQ ? 0 : 6) + shell(i < kQ ? i : i - kQ);
+        return (float)__builtin_bit_cast(_Float16, h) * scale[k];
+    }
+    __device__ __forceinline__ void put(int i, float v) const
+    {
+        const int k = (i < kQ ? 0 : 6) + shell(i < kQ ? i : i - kQ);
+        base[i * kBlockThreads] = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(v * inv_scale[k]));
+    }
+};
+
 // moments, Newton, sensor and relaxation of one fluid cell whose gathered
 // values sit in LDS; the results replace them
-__device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const Park<float> &pk,
-                                        int32_t (&acc)[kStatWords])
+template <class PK>
+__device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const PK &pk, int32_t (&acc)[kStatWords])
 {
     using C = float;
-    using S = float;
+    using S = float;  // shifted storage: the sensor's formula is that of FP32
     C rho = C(d.ref_mass), j0 = C(d.ref_mom[0]), j1 = C(d.ref_mom[1]), j2 = C(d.ref_mom[2]), e = C(d.ref_energy);
     C sg = pk.get(kQ);
     rho += pk.get(0);
@@ -659,6 +699,102 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f32(const SlotTa
         }
     }
     if (stats) {
+        int64_t red[kStatWords];
+#pragma unroll
+        for (int k = 0; k < kStatWords; ++k) red[k] = (k == 1) ? wave_max(acc[k]) : wave_sum(acc[k]);
+        if (lane == 0) {
+            int64_t *p = stats + ((int64_t)blockIdx.x * kWavesPerBlock + wave) * kStatWords;
+#pragma unroll
+            for (int k = 0; k < kStatWords; ++k) p[k] = (k == 1) ? (red[k] > p[k] ? red[k] : p[k]) : p[k] + red[k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP16-shifted step with the FP32 step's structure: 2-byte transfers global
+// -> LDS (each lands zero-extended in the lane's dword of the row), FP32
+// arithmetic through the decoding park, results encoded back into the row
+// words, and full rows leaving as 16-byte-per-lane stores of eight cells
+// (eight rows per instruction).
+template <bool kStats>
+__global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f16(const SlotTable *__restrict__ tab, int j,
+                                                                   int64_t *__restrict__ stats)
+{
+    __shared__ uint32_t park[2 * kQ * kBlockThreads];
+    int32_t acc[kStatWords] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int total = tab->total_blocks;
+    const int xcd = blockIdx.x & 7;
+    const int per_xcd = gridDim.x >> 3;
+    const int lo = (int)(((int64_t)total * xcd) >> 3);
+    const int hi = (int)(((int64_t)total * (xcd + 1)) >> 3);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    f32::lds_float *rows = (f32::lds_float *)park + wave * kSegment;
+    for (int b = lo + (int)(blockIdx.x >> 3); b < hi; b += per_xcd) {
+        const int s = find_slot(tab, b);
+        const SlotDesc &d = tab->slot[s];
+        if (j >= d.steps_todo) continue;
+        const int64_t seg = (int64_t)(b - tab->block_start[s]) * kWavesPerBlock + wave;
+        if (seg >= d.segments) continue;
+        const int segx = (int)(seg % d.nsegx);
+        const int row = (int)(seg / d.nsegx);
+        const int y = row % d.ny;
+        const int z = row / d.ny;
+        const int x = segx * kSegment + lane;
+        const uint32_t cell0 = (uint32_t)(segx * kSegment) + (uint32_t)d.nx * (uint32_t)row;
+        // 16-byte stores of eight cells need a row start on an 8-cell boundary
+        const bool full = (segx * kSegment + kSegment <= d.nx) && (d.nx % 8 == 0);
+        const bool in_grid = x < d.nx;
+        const uint32_t cell = cell0 + (uint32_t)lane;
+        const int par = (d.parity0 + j) & 1;
+        gcbyte *srcb = (gcbyte *)d.buf[par];
+        gbyte *dstb = (gbyte *)d.buf[par ^ 1];
+        bool fluid = in_grid && is_fluid_coord(d, x, y, z);
+        uint64_t links = 0;
+        if (fluid && d.has_links) links = d.links[cell];
+        if (links >> 63) fluid = false;  // solid cells pass through unchanged
+        if (in_grid) f32::gather<2>(d, srcb, x, y, z, cell, links, !fluid, rows);
+        f32::wait_vmem();
+        int32_t it_cell = 0;
+        if (fluid) {
+            const f32::ParkHalf pk{park + threadIdx.x, &d.shell_scale[0][0], &d.shell_inv_scale[0][0]};
+            const int32_t before = acc[0];
+            f32::collide(d, cell, pk, acc);
+            it_cell = acc[0] - before;
+        }
+        if constexpr (kStats) {
+            const int32_t wmax = wave_max(it_cell);
+            acc[8] += lane == 0 ? wmax : 0;
+            acc[9] += lane == 0 ? 1 : 0;
+        }
+        // store the wave's rows
+        const uint64_t nS64 = (uint64_t)d.n * 2;
+        const uint32_t *col = park + wave * kSegment;
+        if (full) {
+            // lanes 8r..8r+7 store row i0 + r, eight cells each
+            const int r = lane >> 3, c8 = (lane & 7) * 8;
+            uint32_t voff = (uint32_t)r * (uint32_t)nS64 + (cell0 + (uint32_t)c8) * 2u;
+            const uint32_t *lcol = col + r * kBlockThreads + c8;
+            __asm__ volatile("" : "+v"(voff));
+#pragma unroll
+            for (int i0 = 0; i0 < 2 * kQ; i0 += 8) {
+                if (i0 + r < 2 * kQ) {
+                    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+                    const v4u w0 = *reinterpret_cast<const v4u *>(lcol + i0 * kBlockThreads);
+                    const v4u w1 = *reinterpret_cast<const v4u *>(lcol + i0 * kBlockThreads + 4);
+                    const v4u v = {(w0.x & 0xffffu) | (w0.y << 16), (w0.z & 0xffffu) | (w0.w << 16),
+                                   (w1.x & 0xffffu) | (w1.y << 16), (w1.z & 0xffffu) | (w1.w << 16)};
+                    __builtin_nontemporal_store(
+                        v, reinterpret_cast<v4u __attribute__((address_space(1))) *>(dstb + (uint64_t)i0 * nS64 + voff));
+                }
+            }
+        } else if (in_grid) {
+#pragma unroll
+            for (int i = 0; i < 2 * kQ; ++i)
+                gstore<uint16_t>(dstb + (uint64_t)i * nS64, cell * 2u, (uint16_t)col[i * kBlockThreads + lane]);
+        }
+    }
+    if constexpr (kStats) {
         int64_t red[kStatWords];
 #pragma unroll
         for (int k = 0; k < kStatWords; ++k) red[k] = (k == 1) ? wave_max(acc[k]) : wave_sum(acc[k]);
@@ -1201,7 +1337,16 @@ hipError_t launch_step(int storage, const SlotTable *tab, int grid, int j, int64
 #else
         return launch_step_t<float>(tab, grid, j, stats, st);
 #endif
-    default: return launch_step_t<_Float16>(tab, grid, j, stats, st);
+    default:
+#if LBM_FP16_DMA
+        if (stats)
+            hipLaunchKernelGGL(step_kernel_f16<true>, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
+        else
+            hipLaunchKernelGGL(step_kernel_f16<false>, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
+        return hipGetLastError();
+#else
+        return launch_step_t<_Float16>(tab, grid, j, stats, st);
+#endif
     }
 }
 
@@ -1218,7 +1363,11 @@ const void *step_kernel_symbol(int storage)
 #else
     case kStoreF32: return reinterpret_cast<const void *>(&step_kernel<float>);
 #endif
+#if LBM_FP16_DMA
+    default: return reinterpret_cast<const void *>(&step_kernel_f16<false>);
+#else
     default: return reinterpret_cast<const void *>(&step_kernel<_Float16>);
+#endif
     }
 }
 
