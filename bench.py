@@ -112,6 +112,28 @@ def measured_traffic(mode: str):
     return t["modes"][mode]["hbm_bytes_per_launch"]
 
 
+def measured_alu(mode: str, ms_per_step: float):
+    """Vector-ALU issue rate of the step kernel: VALU instructions per launch
+    from the committed counter summary (same kernel sources only) over the
+    launch time measured here, against 614.4 G wave instructions/s (one per
+    4 cycles per SIMD, 1024 SIMDs at 2.4 GHz)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    m = t.get("modes", {}).get(mode, {})
+    if "valu_instr_per_launch" not in m:
+        return None
+    peak = 256 * 4 * 2.4e9 / 4.0
+    achieved = m["valu_instr_per_launch"] / (ms_per_step * 1e-3)
+    return {"valu_instr_per_cell": m["valu_instr_per_cell"], "achieved_ginstr_s": achieved / 1e9,
+            "peak_ginstr_s": peak / 1e9, "frac": achieved / peak}
+
+
 def copy_probe(gib=1, reps=5):
     """A plain device-to-device copy of known size (counter calibration)."""
     import torch
@@ -229,6 +251,7 @@ def main():
     roof["traffic"] = measured_traffic(args.mode)
     for m, r in modes.items():
         r["roofline"]["traffic"] = measured_traffic(m)
+        r["alu"] = measured_alu(m, r["ms_per_step"])
     out = {
         "metric": "GLUPS (D3Q39 f+g cell updates per second)",
         "value": main_res["glups"],
@@ -247,6 +270,7 @@ def main():
                    "tau": main_res["tau"], "newton_iterations_per_cell": main_res["newton_iterations_per_cell"],
                    "alpha_hist": main_res["alpha_hist"]},
         "roofline": roof,
+        "alu": measured_alu(args.mode, main_res["ms_per_step"]),
         "cpu_baseline": cpu,
         "modes": modes,
         "serving": serving,

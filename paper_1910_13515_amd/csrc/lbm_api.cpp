@@ -521,7 +521,8 @@ int lbm_step(lbm_ctx *c, int32_t nsteps, lbm_step_stats *stats)
     if (stats) HIP_TRY(c, launch_zero(d_stats, (int64_t)nwaves * kStatWords, c->stream));
     for (int32_t s = 0; s < nsteps; ++s) {
         const int j = (int)((c->steps + s) & 1);
-        HIP_TRY(c, launch_step(c->storage, c->d_table, c->grid, j, d_stats, c->stream));
+        // statistics only when asked for: the kernels without them run lighter
+        HIP_TRY(c, launch_step(c->storage, c->d_table, c->grid, j, stats ? d_stats : nullptr, c->stream));
     }
     c->steps += nsteps;
     if (!stats) return LBM_OK;

@@ -5,6 +5,7 @@ Reads, under one output root:
     trace/        rocprofv3 --kernel-trace --stats of bench.py (all three storage modes)
     pmc_FETCH_SIZE/, pmc_WRITE_SIZE/          one counter per run, same bench command
     pmc_FETCH_SIZE_copy/, pmc_WRITE_SIZE_copy/ the same counters over bench.py --copy-probe
+    pmc_sq/       (optional) SQ_INSTS_VALU, SQ_INSTS_SALU, SQ_INSTS_LDS, SQ_WAVES over the bench command
 
 and writes ``profiles/step_kernel_tgv128.md`` (durations, counter bytes,
 calibration, the commands) and ``profiles/traffic.json`` (HBM bytes per step
@@ -29,8 +30,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PROFILES = os.path.join(ROOT, "profiles")
 
 # kernel-name fragment -> storage mode
-STEP_KERNELS = {"fp64": "step_kernel<double>", "fp32s": "step_kernel_f32", "fp16s": "step_kernelIDF16_"}
-ALT_NAMES = {"fp16s": "step_kernel<_Float16>", "fp64": "step_kernelIdE", "fp32s": "step_kernel_f32"}
+STEP_KERNELS = {"fp64": ("step_kernel_f64", "step_kernel<double>", "step_kernelIdE"),
+                "fp32s": ("step_kernel_f32",),
+                "fp16s": ("step_kernel_f16", "step_kernel<_Float16>", "step_kernelIDF16_")}
 BYTES_PER_CELL = {"fp64": 2 * 78 * 8 + 2 * 13 * 8, "fp32s": 2 * 78 * 4 + 2 * 13 * 4, "fp16s": 2 * 78 * 2 + 2 * 13 * 4}
 CELLS = 128 ** 3
 COPY_BYTES = 1 << 30
@@ -38,8 +40,8 @@ COPY_REPS = 5
 
 
 def _mode_of(name: str):
-    for m in STEP_KERNELS:
-        if STEP_KERNELS[m] in name or ALT_NAMES[m] in name:
+    for m, frags in STEP_KERNELS.items():
+        if any(f in name for f in frags):
             return m
     return None
 
@@ -92,6 +94,32 @@ def counter_total(root, sub, counter, select):
     return tot
 
 
+# VALU issue ceiling: one wave64 vector instruction per 4 cycles per SIMD
+# (16 lanes), 4 SIMDs x 256 CUs at 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4.0
+
+
+def sq_counters(root):
+    """Mean SQ instruction counts per dispatch of each step kernel (optional run)."""
+    try:
+        path = _one(root, "pmc_sq/**/tgv128_counter_collection.csv")
+    except FileNotFoundError:
+        return {}
+    sums, counts = {}, {}
+    with open(path) as fh:
+        for row in csv.DictReader(fh):
+            m = _mode_of(row["Kernel_Name"])
+            if m is None:
+                continue
+            key = (m, row["Counter_Name"])
+            sums[key] = sums.get(key, 0.0) + float(row["Counter_Value"])
+            counts[key] = counts.get(key, 0) + 1
+    out = {}
+    for (m, c), v in sums.items():
+        out.setdefault(m, {})[c] = v / counts[(m, c)]
+    return out
+
+
 def summarize(root, commands=None):
     sys.path.insert(0, ROOT)
     import bench  # the hash of the device sources the profile belongs to
@@ -121,6 +149,17 @@ def summarize(root, commands=None):
             "hbm_read_bytes": fb, "hbm_write_bytes": wb, "hbm_bytes_per_launch": fb + wb,
             "hbm_GBps": (fb + wb) / avg_s / 1e9, "traffic_over_algorithmic": (fb + wb) / alg,
         }
+    sq = sq_counters(root)
+    for m, v in modes.items():
+        if m in sq and "SQ_INSTS_VALU" in sq[m]:
+            valu = sq[m]["SQ_INSTS_VALU"]
+            v["valu_instr_per_launch"] = valu
+            v["valu_instr_per_cell"] = valu / CELLS
+            v["valu_issue_floor_us"] = valu / VALU_ISSUE_PEAK * 1e6
+            v["valu_issue_frac"] = (valu / (v["avg_ns"] * 1e-9)) / VALU_ISSUE_PEAK
+            for c in ("SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_WAVES"):
+                if c in sq[m]:
+                    v[c.lower()] = sq[m][c]
     data = {"kernel_hash": bench.kernel_hash(), "workload": "periodic 128^3 Taylor-Green vortex, Ma 0.5, Re 1600",
             "cells_per_launch": CELLS,
             "calibration": {"copy_bytes_each_way": COPY_BYTES, "copies": COPY_REPS,
@@ -143,6 +182,15 @@ def summarize(root, commands=None):
                      f"{v['algorithmic_GBps']:.0f} | {v['algorithmic_GBps'] / 8000:.3f} | {v['fetch_kib_raw']:.0f} | "
                      f"{v['write_kib_raw']:.0f} | {v['hbm_bytes_per_launch']:.4g} | {v['hbm_GBps']:.0f} | "
                      f"{v['traffic_over_algorithmic']:.3f} |")
+    if any("valu_instr_per_cell" in v for v in modes.values()):
+        lines += ["", "Vector ALU issue (rocprofv3 SQ_INSTS_VALU per dispatch).  Ceiling: one wave64 VALU "
+                  "instruction per 4 cycles per SIMD, 1024 SIMDs at 2.4 GHz = 614.4 G instructions/s.", "",
+                  "| storage | VALU instr / cell | VALU issue floor (us) | kernel avg (us) | issue rate / ceiling |",
+                  "|---|---|---|---|---|"]
+        for m, v in modes.items():
+            if "valu_instr_per_cell" in v:
+                lines.append(f"| {m} | {v['valu_instr_per_cell']:.0f} | {v['valu_issue_floor_us']:.0f} | "
+                             f"{v['avg_ns'] / 1e3:.0f} | {v['valu_issue_frac']:.2f} |")
     c = data["calibration"]
     lines += ["", "Counter calibration (plain device copy of 1 GiB, `bench.py --copy-probe`): "
               f"FETCH_SIZE reads {c['fetch_kib_per_copy']:.0f} KiB per copy dispatch (factor {c['fetch_factor']:.3f}), "
