@@ -370,3 +370,72 @@ def test_full_size_airfoil_step(orc, lbm):
     _log(f"airfoil: moments {em}, populations f {ef:.2e} g {eg:.2e}")
     assert max(em) <= TOL and ef <= TOL and eg <= TOL
     s.close()
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 7, 3), (5, 1, 1), (64, 1, 2), (65, 2, 1), (256, 2, 2)])
+def test_degenerate_and_segment_edge_grids(orc, lbm, shape):
+    """Grids where every velocity wraps onto few cells (1x1x1, single-cell
+    axes), exactly one full 64-cell row segment, a full segment plus a
+    one-cell tail, and several full segments: one step from a random state
+    against the oracle at 1e-12."""
+    _log(f"edge grid {shape}")
+    f, g, lam = oracle_state(orc, shape, 1.4, seed=41, amplitudes=(1e-3, 3e-2))
+    o, s = _pair(orc, lbm, shape)
+    o.set_state(f, g, lam)
+    s.set_state(f, g, lam)
+    o.step(1)
+    st = s.step(1, stats=True)
+    fg, gg, _ = s.get_state()
+    assert max_rel(fg, o.f) < TOL and max_rel(gg, o.g) < TOL
+    assert st.failed == 0 and list(st.alpha_hist) == list(o.stats.alpha_hist)
+    s.close()
+
+
+@pytest.mark.parametrize("gamma", [5.0 / 3.0, 1.1])
+def test_extreme_heat_capacity_ratios(orc, lbm, gamma):
+    """gamma = 5/3 leaves no internal degrees of freedom (delta = 0: g^eq = 0);
+    gamma = 1.1 gives delta = 17.  Two steps against the oracle."""
+    shape = (12, 6, 5)
+    _log(f"gamma {gamma}")
+    f, g, lam = oracle_state(orc, shape, gamma, seed=43, amplitudes=(1e-3, 3e-2))
+    o, s = _pair(orc, lbm, shape, gamma=gamma)
+    o.set_state(f, g, lam)
+    s.set_state(f, g, lam)
+    o.step(2)
+    st = s.step(2, stats=True)
+    fg, gg, _ = s.get_state()
+    assert max_rel(fg, o.f) < TOL
+    assert np.max(np.abs(gg - o.g)) <= TOL * max(np.abs(o.g).max(), np.abs(o.f).max())
+    m, t = s.moments()
+    mo, to = o.moments()
+    assert max(moment_error(m, mo)) < TOL
+    assert st.failed == 0
+    s.close()
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32s", "fp16s"])
+def test_checkpoint_restart_is_bitwise(lbm, storage):
+    """A state read with lbm_get_state and written into a fresh solve with
+    lbm_set_state continues exactly as the original run."""
+    n = 24
+    gamma, T0, ma = 1.4, 0.5, 0.5
+    U = ma * np.sqrt(gamma * T0)
+    fields = inputs.taylor_green_fields(n, U, T0)
+    kw = dict(gamma=gamma, mach=ma, reynolds=1600.0, length_ref=n / (2 * np.pi), T_ref=T0, u_dir=(1, 0, 0),
+              kn_relax=True, storage=storage)
+    a = lbm.Solver((n, n, n), fields=fields, **kw)
+    a.step(7)
+    ck = a.get_state()
+    a.step(5)
+    fa, ga, la = a.get_state()
+    ma_, ta = a.moments()
+    b = lbm.Solver((n, n, n), fields=fields, **kw)
+    b.step(3)  # a different buffer parity and warm start, overwritten below
+    b.set_state(*ck)
+    b.step(5)
+    fb, gb, lb = b.get_state()
+    mb, tb = b.moments()
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb) and np.array_equal(la, lb)
+    assert np.array_equal(ma_, mb) and np.array_equal(ta, tb)
+    a.close()
+    b.close()
