@@ -134,8 +134,11 @@ int lbm_create(const lbm_params *params, void *dev_arena, int64_t arena_bytes, v
 
 /* Advances nsteps >= 0 time steps (fused pull-stream and collide, Sec. 3).
  * Asynchronous on the stream when stats is NULL; otherwise synchronises and
- * fills *stats.  Returns LBM_E_NEWTON if a cell failed to converge (counted in
- * stats; the state stays defined, holding the last Newton iterate). */
+ * fills *stats.  A fluid cell whose 13 multipliers are not found (warm start,
+ * then cold start) is not collided in that step: its gathered populations are
+ * stored unchanged and its multipliers kept, so every moment of the cell is
+ * conserved.  With stats, returns LBM_E_NEWTON when that happened (the number
+ * of such cell updates is stats->failed); the state stays defined. */
 int lbm_step(lbm_ctx *ctx, int32_t nsteps, lbm_step_stats *stats);
 
 /* Macroscopic fields of the current state, in FP64.  out_host (nullable):
@@ -145,6 +148,16 @@ int lbm_step(lbm_ctx *ctx, int32_t nsteps, lbm_step_stats *stats);
  * g_i) / 2), summed over fluid cells in a fixed order.  Synchronises.  Returns
  * LBM_E_NONFINITE if any fluid-cell moment is not finite. */
 int lbm_moments(lbm_ctx *ctx, double *out_host, double *totals);
+
+/* Per-cell diagnostics of the next step, from the current state, which is
+ * left unchanged: the Knudsen sensor eps of Eq. (eq:DeltaAvg), whose maps
+ * Sec. 4 shows for the airfoil (Fig. fig:naca-knudsen), and the number of
+ * Newton iterations the cell's solve takes (warm start; the cold restart's
+ * count when that is used).  eps_out (nullable): N doubles, NaN outside fluid
+ * cells and where the solve fails; iters_out (nullable): N int32, -1 outside
+ * fluid cells, the iteration cap where the solve fails.  Uses the moments
+ * scratch of the arena.  Synchronises. */
+int lbm_diagnostics(lbm_ctx *ctx, double *eps_out, int32_t *iters_out);
 
 /* Copies the state to host FP64 arrays (each nullable): f and g as [39][N],
  * multipliers as [13][N].  Shifted storage is decoded.  Synchronises. */

@@ -12,6 +12,7 @@ namespace lbm13 {
 
 hipError_t launch_step(int storage, const SlotTable *tab, int grid, int j, int64_t *stats, hipStream_t st);
 const void *step_kernel_symbol(int storage);
+hipError_t launch_diag(int storage, const SlotTable *tab, int grid, int j, double *diag, hipStream_t st);
 hipError_t launch_init(int storage, const SlotDesc &d, const double *fields, unsigned long long *failed,
                        hipStream_t st);
 hipError_t launch_single_equilibrium(double rho, const double u[3], double T, double tol, int maxit, double *out,

@@ -563,6 +563,25 @@ int lbm_moments(lbm_ctx *c, double *out_host, double *totals)
     return LBM_OK;
 }
 
+int lbm_diagnostics(lbm_ctx *c, double *eps_out, int32_t *iters_out)
+{
+    if (!c) return fail(nullptr, LBM_E_INVAL, "ctx is NULL");
+    const int64_t n = c->desc.n;
+    double *d_diag = at<double>(c->arena, c->layout.fields);  // 2n of the 5n moment doubles
+    const int grid = (int)std::min<int64_t>(c->desc.blocks, kMaxGrid);
+    HIP_TRY(c, launch_diag(c->storage, c->d_table, std::max(grid, 1), (int)(c->steps & 1), d_diag, c->stream));
+    if (eps_out) HIP_TRY(c, hipMemcpyAsync(eps_out, d_diag, n * 8, hipMemcpyDeviceToHost, c->stream));
+    std::vector<double> it;
+    if (iters_out) {
+        it.resize(n);
+        HIP_TRY(c, hipMemcpyAsync(it.data(), d_diag + n, n * 8, hipMemcpyDeviceToHost, c->stream));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (iters_out)
+        for (int64_t k = 0; k < n; ++k) iters_out[k] = (int32_t)it[k];
+    return LBM_OK;
+}
+
 int lbm_get_state(lbm_ctx *c, double *f, double *g, double *lam)
 {
     if (!c) return fail(nullptr, LBM_E_INVAL, "ctx is NULL");

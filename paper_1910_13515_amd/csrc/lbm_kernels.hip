@@ -256,15 +256,23 @@ __device__ __forceinline__ C eps_sum(const SlotDesc &d, C rho, C f0, const C *fp
 using VelSeq = std::make_integer_sequence<int, kQ>;
 
 // One fluid cell: gather, moments, Newton, sensor, BGK, store.  (y, z) are
-// uniform across the wave; x is the lane's coordinate.
-template <class S>
+// uniform across the wave; x is the lane's coordinate.  kDiag: stop after the
+// sensor and write eps (NaN where the solve fails) to diag[cell] and the
+// Newton iterations to diag[n + cell]; nothing else is written.
+template <class S, bool kDiag = false>
 __device__ __forceinline__ void update_cell(const SlotDesc &d, const S *src, S *dst, int x, int y, int z,
                                             uint32_t cell, const Park<typename StoreTraits<S>::C> &pk,
-                                            int32_t (&acc)[kStatWords])
+                                            int32_t (&acc)[kStatWords], double *diag = nullptr)
 {
     using C = typename StoreTraits<S>::C;
     const uint64_t links = d.has_links ? d.links[cell] : 0ull;
-    if (links >> 63) return;  // solid
+    if (links >> 63) {  // solid
+        if constexpr (kDiag) {
+            diag[cell] = __builtin_nan("");
+            diag[d.n + cell] = -1.0;
+        }
+        return;
+    }
 
     // byte offsets of the source coordinates x - c, c = -3..3, per axis
     const uint32_t nx = (uint32_t)d.nx, nxy = (uint32_t)d.nx * (uint32_t)d.ny;
@@ -351,6 +359,11 @@ __device__ __forceinline__ void update_cell(const SlotDesc &d, const S *src, S *
     // against the finite values the solver leaves): gathered values stored
     // unchanged, multipliers kept for the next warm start
     const bool failed = status == kFailed;
+    if constexpr (kDiag) {
+        diag[cell] = failed ? __builtin_nan("") : (double)eps;
+        diag[d.n + cell] = (double)iters;
+        return;
+    }
     const C omega = failed ? C(0) : C(br == 0 ? d.omega[0] : br == 1 ? d.omega[1] : br == 2 ? d.omega[2] : d.omega[3]);
     const C dT = C(d.delta) * T;
 
@@ -434,6 +447,42 @@ __global__ __launch_bounds__(kBlockThreads, StoreTraits<S>::kWavesPerSimd) void 
             int64_t *p = stats + ((int64_t)blockIdx.x * kWavesPerBlock + wave) * kStatWords;
 #pragma unroll
             for (int k = 0; k < kStatWords; ++k) p[k] = (k == 1) ? (red[k] > p[k] ? red[k] : p[k]) : p[k] + red[k];
+        }
+    }
+}
+
+// Diagnostics of the next step of one solve (slot 0 of tab, launch index j):
+// the Knudsen sensor and the Newton iterations of every cell, from the
+// current state, which is left unchanged.  diag: eps[n] then iterations[n]
+// (FP64; NaN / -1 outside fluid cells, NaN eps where the solve fails).
+template <class S>
+__global__ __launch_bounds__(kBlockThreads, StoreTraits<S>::kWavesPerSimd) void diag_kernel(
+    const SlotTable *__restrict__ tab, int j, double *__restrict__ diag)
+{
+    using C = typename StoreTraits<S>::C;
+    __shared__ C park[2 * kQ * kBlockThreads];
+    const Park<C> pk{park + threadIdx.x};
+    int32_t acc[kStatWords] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const SlotDesc &d = tab->slot[0];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    for (int b = blockIdx.x; b < d.blocks; b += gridDim.x) {
+        const int64_t seg = (int64_t)b * kWavesPerBlock + wave;
+        if (seg >= d.segments) continue;
+        const int segx = (int)(seg % d.nsegx);
+        const int row = (int)(seg / d.nsegx);
+        const int y = row % d.ny;
+        const int z = row / d.ny;
+        const int x = segx * kSegment + lane;
+        if (x >= d.nx) continue;
+        const uint32_t cell = (uint32_t)x + (uint32_t)d.nx * ((uint32_t)y + (uint32_t)d.ny * (uint32_t)z);
+        if (is_fluid_coord(d, x, y, z)) {
+            const int par = (d.parity0 + j) & 1;
+            const S *src = static_cast<const S *>(d.buf[par]);
+            update_cell<S, true>(d, src, nullptr, x, y, z, cell, pk, acc, diag);
+        } else {
+            diag[cell] = __builtin_nan("");
+            diag[d.n + cell] = -1.0;
         }
     }
 }
@@ -1314,6 +1363,16 @@ template <class S>
 static hipError_t launch_step_t(const SlotTable *tab, int grid, int j, int64_t *stats, hipStream_t st)
 {
     hipLaunchKernelGGL(step_kernel<S>, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(int storage, const SlotTable *tab, int grid, int j, double *diag, hipStream_t st)
+{
+    switch (storage) {
+    case kStoreF64: hipLaunchKernelGGL(diag_kernel<double>, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, diag); break;
+    case kStoreF32: hipLaunchKernelGGL(diag_kernel<float>, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, diag); break;
+    default: hipLaunchKernelGGL(diag_kernel<_Float16>, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, diag); break;
+    }
     return hipGetLastError();
 }
 

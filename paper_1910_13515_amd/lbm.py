@@ -36,6 +36,7 @@ LBM_FACE_EQUILIBRIUM = 1
 LBM_FACE_NEUMANN = 2
 
 EXPORTED = ["lbm_version", "lbm_velocities", "lbm_required_bytes", "lbm_create", "lbm_step", "lbm_moments",
+            "lbm_diagnostics",
             "lbm_get_state", "lbm_set_state", "lbm_get_info", "lbm_destroy", "lbm_last_error",
             "lbm_pool_overhead_bytes", "lbm_pool_create", "lbm_pool_admit", "lbm_pool_launch", "lbm_pool_wait",
             "lbm_pool_run", "lbm_pool_slot_progress", "lbm_pool_moments", "lbm_pool_release", "lbm_pool_get_info",
@@ -112,6 +113,8 @@ def load() -> ctypes.CDLL:
     L.lbm_step.argtypes = [vp, i32, ctypes.POINTER(lbm_step_stats)]
     L.lbm_moments.restype = ctypes.c_int
     L.lbm_moments.argtypes = [vp, vp, vp]
+    L.lbm_diagnostics.restype = ctypes.c_int
+    L.lbm_diagnostics.argtypes = [vp, vp, vp]
     L.lbm_get_state.restype = ctypes.c_int
     L.lbm_get_state.argtypes = [vp, vp, vp, vp]
     L.lbm_set_state.restype = ctypes.c_int
@@ -205,6 +208,14 @@ def lbm_moments(ctx, n: int, fields: bool = True):
     if code != LBM_E_NONFINITE:
         _check(code, ctx)
     return (None if out is None else out.reshape(5, n)), tot, code
+
+
+def lbm_diagnostics(ctx, n: int):
+    """(eps[N], iterations[N]) of the next step from the current state."""
+    eps = np.empty(n)
+    its = np.empty(n, dtype=np.int32)
+    _check(load().lbm_diagnostics(ctx, _ptr(eps), _ptr(its)), ctx)
+    return eps, its
 
 
 def lbm_get_state(ctx, n: int):
@@ -317,6 +328,10 @@ class Solver:
 
     def get_state(self):
         return lbm_get_state(self.ctx, self.n)
+
+    def diagnostics(self):
+        """Knudsen sensor and Newton iterations of the next step, per cell."""
+        return lbm_diagnostics(self.ctx, self.n)
 
     def set_state(self, f, g, lam):
         lbm_set_state(self.ctx, f, g, lam)

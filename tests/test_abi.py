@@ -114,3 +114,7 @@ def test_pool_arguments_validated_without_device(L):
     assert L.lbm_pool_release(None, 0) == lbm.LBM_E_INVAL
     assert L.lbm_pool_destroy(None) == lbm.LBM_E_INVAL
     assert L.lbm_pool_last_error(None)
+
+
+def test_diagnostics_null_context(L):
+    assert L.lbm_diagnostics(None, None, None) == lbm.LBM_E_INVAL

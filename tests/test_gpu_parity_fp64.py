@@ -439,3 +439,67 @@ def test_checkpoint_restart_is_bitwise(lbm, storage):
     assert np.array_equal(ma_, mb) and np.array_equal(ta, tb)
     a.close()
     b.close()
+
+
+def _diag_compare(o, s, shape, eps_values=True):
+    before = s.get_state()
+    eps_g, it_g = s.diagnostics()
+    after = s.get_state()
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)  # diagnostics leave the state unchanged
+    it_o, eps_o = o.step(1, diagnostics=True)
+    np.testing.assert_array_equal(np.isnan(eps_g), np.isnan(eps_o))
+    ok = ~np.isnan(eps_o)
+    # the branch of alpha(eps) everywhere
+    thr = [1e-2, 1e-1, 1.0]
+    np.testing.assert_array_equal(np.digitize(eps_g[ok], thr), np.digitize(eps_o[ok], thr))
+    # eps itself: next to states without equilibrium the multipliers are
+    # ill-conditioned (a residual bound fixes them only loosely) and eps,
+    # dominated by 1/f^eq of tiny populations, follows; there only the
+    # branch is compared
+    if eps_values:
+        assert np.max(np.abs(eps_g[ok] - eps_o[ok]) / np.abs(eps_o[ok])) < 1e-10
+    np.testing.assert_array_equal(it_g, it_o)
+    return eps_g, it_g
+
+
+@pytest.mark.parametrize("with_obstacle", [False, True])
+def test_diagnostics_match_oracle(orc, lbm, with_obstacle):
+    """Per-cell Knudsen sensor and Newton iterations of the next step
+    (lbm_diagnostics) against the oracle's diagnostics of that step."""
+    shape = (40, 20, 6) if with_obstacle else (70, 5, 4)
+    solid = inputs.sphere_mask(*shape, center=(18.5, 9.5, 2.5), radius=4.2) if with_obstacle else None
+    faces = (orc.FACE_EQUILIBRIUM, orc.FACE_NEUMANN, 0, 0, 0, 0) if with_obstacle else (0,) * 6
+    f, g, lam = oracle_state(orc, shape, 1.4, seed=47, amplitudes=(1e-3, 3e-2, 0.3))
+    o, s = _pair(orc, lbm, shape, faces=faces, solid=solid)
+    o.set_state(f, g, lam)
+    s.set_state(f, g, lam)
+    eps, its = _diag_compare(o, s, shape)
+    assert np.nanmax(eps) > 1e-2  # several alpha branches are exercised
+    if with_obstacle:
+        assert np.sum(its == -1) >= int(solid.sum())
+    s.close()
+
+
+def test_diagnostics_of_cells_without_equilibrium(orc, lbm):
+    shape = (16, 4, 4)
+    nx = shape[0]
+    n = int(np.prod(shape))
+    rho, u, T = inputs.uniform_fields(n, 1.0, [0.1, 0.0, 0.0], 0.5)
+    o = orc.Oracle(*shape, gamma=1.4, tau=0.6, newton_tol=1e-13, newton_maxit=30)
+    o.init(rho, u, T)
+    f, g, lam = o.f.copy(), o.g.copy(), o.lam.copy()
+    c = orc.velocities()
+    q = (c ** 2).sum(1)
+    F = f.reshape(39, n)
+    G = g.reshape(39, n).copy()
+    x = np.arange(n) % nx
+    slab = (x >= 2) & (x <= 9)
+    e_now = (F * q[:, None]).sum(0) + G.sum(0)
+    G[:, slab] += ((1.0 * 0.01 + 5.0 * 0.1 - e_now[slab]) / 39.0)[None, :]
+    o.set_state(f, G.reshape(-1), lam)
+    s = lbm.Solver(shape, storage="fp64", tau=0.6, newton_tol=1e-13, newton_maxit=30)
+    s.set_state(f, G.reshape(-1), lam)
+    eps, its = _diag_compare(o, s, shape, eps_values=False)
+    assert np.isnan(eps).sum() > 0 and np.all(its[np.isnan(eps)] == 30)
+    s.close()
