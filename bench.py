@@ -153,7 +153,7 @@ SERVING_MIX = dict(tube_cells=(200, 4000), box_cells=(64, 192), steps=(200, 2000
                    mach=(0.3, 1.5), reynolds=(1e3, 1e4))
 
 
-def serving_leg(count, rate, seed=2024, arena_gib=96, max_slots=64, graph_steps=32, sched="srpt", sequential=True):
+def serving_leg(count, rate, seed=2024, arena_gib=96, max_slots=64, graph_steps=32, sched="vft", sequential=True):
     """The serving mix (seeded Poisson arrivals of tubes and boxes, FP32
     shifted storage): continuous batching in the pool against the same trace
     solved one at a time with the plain calls."""

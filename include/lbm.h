@@ -199,10 +199,14 @@ typedef struct lbm_pool lbm_pool;
 
 typedef enum {
     LBM_SCHED_ALL = 0,   /* every slot with steps left runs in every round */
-    LBM_SCHED_SRPT = 1   /* slots by least remaining work (fluid cells x steps
+    LBM_SCHED_SRPT = 1,  /* slots by least remaining work (fluid cells x steps
                             left); the first always, further ones while the
-                            cells per step stay within max(fill_cells, cells of
-                            the first); the rest wait for a later round */
+                            cells per step stay within the first's cells plus
+                            fill_cells; the rest wait for a later round */
+    LBM_SCHED_VFT = 2    /* as SRPT, ordered by virtual finish time: admission
+                            time + remaining work / throughput of recent full
+                            rounds (small solves first, large ones not passed
+                            indefinitely) */
 } lbm_sched;
 
 typedef struct {
@@ -224,7 +228,7 @@ int64_t lbm_pool_overhead_bytes(int32_t max_slots);
 /* Creates a pool over a caller-owned device arena (256-byte aligned).  The
  * slots' footprints (lbm_required_bytes) are carved from the arena beyond the
  * pool overhead.  storage: lbm_storage shared by all slots.  graph_steps in
- * [1, 4096].  sched: lbm_sched.  fill_cells: SRPT bound, 0 = four row blocks
+ * [1, 4096].  sched: lbm_sched.  fill_cells: SRPT/VFT bound, 0 = four row blocks
  * per resident workgroup of the persistent grid.  hip_stream NULL: the pool
  * creates its own stream.  Captures the graph.  LBM_E_NOMEM when the arena
  * cannot hold the overhead. */

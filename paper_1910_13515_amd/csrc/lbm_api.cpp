@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -664,7 +665,8 @@ struct PoolSlot {
     lbm_ctx *ctx = nullptr;
     int64_t off = 0, bytes = 0;
     int64_t steps_total = 0, steps_left = 0;
-    int64_t admitted_seq = 0;  // admission order (ties of the SRPT order)
+    int64_t admitted_seq = 0;  // admission order (ties of the orders below)
+    double admitted_at = 0.0;  // host clock at admission (s)
 };
 
 // first-fit allocator over [base, base + size) in 256-byte units
@@ -724,6 +726,8 @@ struct RangeHeap {
 struct lbm_pool {
     int storage = 0, max_slots = 0, graph_steps = 1, grid = 8, sched = LBM_SCHED_ALL;
     int64_t fill_cells = 0;
+    double rate = 4e9;          // cell updates per second of recent rounds (LBM_SCHED_VFT)
+    double launched_at = 0.0;   // host clock of the round in flight
     hipStream_t stream = nullptr;        // rounds (the captured graph)
     hipStream_t admit_stream = nullptr;  // admission, moments, release
     hipEvent_t admitted = nullptr;       // last admission's work, waited for by the next round
@@ -777,24 +781,35 @@ void pool_free(lbm_pool *p)
 
 bool slot_ok(const lbm_pool *p, int32_t slot) { return p && slot >= 0 && slot < p->max_slots && p->slots[slot].used; }
 
+double host_seconds()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 // The slots the next round advances.  LBM_SCHED_ALL: every slot with steps
 // left (processor sharing).  LBM_SCHED_SRPT: slots in order of remaining work
-// (fluid cells x steps left, admission order on ties), the first always, the
-// next ones while the cells per step stay within max(fill_cells, cells of the
-// first): small solves finish first and in few launches, and a launch is
-// never slowed down by more than what fills the device anyway.
+// (fluid cells x steps left).  LBM_SCHED_VFT: slots in order of virtual finish
+// time, admission time + remaining work / recent throughput (small solves
+// still go first, but a large one is not passed by solves admitted after it
+// would have finished alone).  Ties by admission order.  For both orders the
+// first slot always runs and the next ones join while the cells per step stay
+// within the first slot's plus fill_cells: a launch is never slowed down by
+// more than what fills the device anyway.
 std::vector<int> pick_round(const lbm_pool *p)
 {
     std::vector<int> run;
     for (int i = 0; i < p->max_slots; ++i)
         if (p->slots[i].used && p->slots[i].steps_left > 0) run.push_back(i);
-    if (p->sched != LBM_SCHED_SRPT || run.size() < 2) return run;
-    auto work = [&](int i) { return p->slots[i].ctx->fluid_cells * p->slots[i].steps_left; };
+    if (p->sched == LBM_SCHED_ALL || run.size() < 2) return run;
+    auto work = [&](int i) { return (double)p->slots[i].ctx->fluid_cells * (double)p->slots[i].steps_left; };
+    auto key = [&](int i) {
+        return p->sched == LBM_SCHED_SRPT ? work(i) : p->slots[i].admitted_at + work(i) / p->rate;
+    };
     std::sort(run.begin(), run.end(), [&](int a, int b) {
-        const int64_t wa = work(a), wb = work(b);
-        return wa != wb ? wa < wb : p->slots[a].admitted_seq < p->slots[b].admitted_seq;
+        const double ka = key(a), kb = key(b);
+        return ka != kb ? ka < kb : p->slots[a].admitted_seq < p->slots[b].admitted_seq;
     });
-    const int64_t cap = std::max(p->fill_cells, p->slots[run[0]].ctx->desc.n);
+    const int64_t cap = p->slots[run[0]].ctx->desc.n + p->fill_cells;
     std::vector<int> out;
     int64_t cells = 0;
     for (int i : run) {
@@ -824,7 +839,8 @@ int lbm_pool_create(int32_t storage, int32_t max_slots, int32_t graph_steps, int
     if (storage < LBM_STORE_FP64 || storage > LBM_STORE_FP16_SHIFTED) return fail(nullptr, LBM_E_INVAL, "unknown storage");
     if (max_slots < 1 || max_slots > kMaxSlots) return fail(nullptr, LBM_E_INVAL, "max_slots out of range");
     if (graph_steps < 1 || graph_steps > 4096) return fail(nullptr, LBM_E_INVAL, "graph_steps out of range");
-    if (sched != LBM_SCHED_ALL && sched != LBM_SCHED_SRPT) return fail(nullptr, LBM_E_INVAL, "unknown scheduling policy");
+    if (sched != LBM_SCHED_ALL && sched != LBM_SCHED_SRPT && sched != LBM_SCHED_VFT)
+        return fail(nullptr, LBM_E_INVAL, "unknown scheduling policy");
     if (fill_cells < 0) return fail(nullptr, LBM_E_INVAL, "fill_cells must be >= 0");
     if (!dev_arena || reinterpret_cast<uintptr_t>(dev_arena) % kAlign != 0)
         return fail(nullptr, LBM_E_INVAL, "dev_arena must be a 256-byte aligned device pointer");
@@ -936,6 +952,7 @@ int lbm_pool_admit(lbm_pool *p, const lbm_params *params, int32_t nsteps, int32_
     s.steps_total = nsteps;
     s.steps_left = nsteps;
     s.admitted_seq = p->seq++;
+    s.admitted_at = host_seconds();
     *slot_out = slot;
     return LBM_OK;
 }
@@ -969,6 +986,7 @@ int lbm_pool_launch(lbm_pool *p, int32_t *nlaunched)
     for (int i : run) p->slots[i].in_round = true;
     p->round = run;
     p->in_flight = true;
+    p->launched_at = host_seconds();
     if (nlaunched) *nlaunched = n;
     return LBM_OK;
 }
@@ -979,13 +997,16 @@ int lbm_pool_wait(lbm_pool *p, int32_t *finished, int32_t *nfinished)
     if (nfinished) *nfinished = 0;
     if (!p->in_flight) return LBM_OK;
     const hipError_t e = hipStreamSynchronize(p->stream);
+    const double dt = host_seconds() - p->launched_at;
     p->in_flight = false;
     int nf = 0;
+    double done = 0.0;
     for (int i : p->round) {
         PoolSlot &s = p->slots[i];
         s.in_round = false;
         if (e != hipSuccess) continue;
         const int64_t adv = std::min<int64_t>(p->graph_steps, s.steps_left);
+        done += (double)s.ctx->fluid_cells * (double)adv;
         s.ctx->steps += adv;
         s.steps_left -= adv;
         if (s.steps_left == 0) {
@@ -994,6 +1015,9 @@ int lbm_pool_wait(lbm_pool *p, int32_t *finished, int32_t *nfinished)
         }
     }
     p->round.clear();
+    // throughput of rounds that fill the device (small rounds are launch-bound)
+    if (e == hipSuccess && dt > 0.0 && done >= (double)p->fill_cells * p->graph_steps)
+        p->rate = 0.7 * p->rate + 0.3 * (done / dt);
     if (e != hipSuccess) return pool_fail(p, LBM_E_DEVICE, std::string("round failed: ") + hipGetErrorString(e));
     if (nfinished) *nfinished = nf;
     return LBM_OK;

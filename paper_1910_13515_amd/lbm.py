@@ -74,7 +74,8 @@ class lbm_info(ctypes.Structure):
 
 LBM_SCHED_ALL = 0
 LBM_SCHED_SRPT = 1
-SCHED = {"all": LBM_SCHED_ALL, "srpt": LBM_SCHED_SRPT}
+LBM_SCHED_VFT = 2
+SCHED = {"all": LBM_SCHED_ALL, "srpt": LBM_SCHED_SRPT, "vft": LBM_SCHED_VFT}
 
 
 class lbm_pool_info(ctypes.Structure):

@@ -59,7 +59,7 @@ class Pool:
     """A serving pool over a torch-owned device arena."""
 
     def __init__(self, arena_bytes: int, storage: str = "fp32s", max_slots: int = 64, graph_steps: int = 32,
-                 sched: str = "srpt", fill_cells: int = 0, stream=None):
+                 sched: str = "vft", fill_cells: int = 0, stream=None):
         import torch
         L = _lib()
         self.storage = storage

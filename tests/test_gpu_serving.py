@@ -22,7 +22,7 @@ def _first(kind, seed=3, **kw):
 
 
 @pytest.mark.parametrize("storage,sched", [("fp64", "all"), ("fp64", "srpt"), ("fp32s", "srpt"), ("fp16s", "srpt"),
-                                           ("fp32s", "all")])
+                                           ("fp32s", "all"), ("fp32s", "vft")])
 def test_mix_equals_alone_bitwise(storage, sched):
     from paper_1910_13515_amd import serve
     trace = _trace(11, 9)
