@@ -86,11 +86,13 @@ def run_mode(mode, n, steps, warmup):
     }
 
 
-KERNEL_SOURCES = ["lbm_kernels.hip", "equilibrium.h", "d3q39.h", "slot.h"]
+# device sources, and the host layer that sets their run-time parameters
+# (default Newton tolerances change the instruction counts)
+KERNEL_SOURCES = ["lbm_kernels.hip", "equilibrium.h", "d3q39.h", "slot.h", "lbm_api.cpp"]
 
 
 def kernel_hash() -> str:
-    """Hash of the device sources, to tie counter data to the kernel it came from."""
+    """Hash of the kernel sources, to tie counter data to the kernel it came from."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1910_13515_amd", "csrc", f), "rb") as fh:
