@@ -226,8 +226,8 @@ static void cold_guess(const double u[3], double T, double lam[NL])
  * tol * max(1, max_k |M_k| / rho).  Globalisation (reading; the paper says
  * only "standard multivariate Newton-Raphson"): the step is halved while the
  * Euclidean norm of G does not decrease; if the full step does not decrease
- * it while max_k |G_k| is within 8 times the bound, the step is taken and the
- * solve stops (round-off floor).  On return lam and feq (per unit density) hold the last
+ * it while max_k |G_k| before and after it is within 8 times the bound, the
+ * step is taken and the solve stops (round-off floor).  On return lam and feq (per unit density) hold the last
  * iterate.  Returns the number of accepted updates,
  * or -1 when the cap is reached, J is not positive definite, or a value is
  * not finite. */
@@ -250,13 +250,13 @@ static int newton(const double m[NL], double lam[NL], double feq[NQ], double tol
         n0 = norm_2(G);
         {
             double t = 1.0;
-            /* reading: when the full step does not lower the residual and the
-             * iterate is already within 8 times the tolerance, the residual
-             * sits at the round-off floor of the arithmetic; the step is
-             * taken and the solve stops */
+            /* reading: when the full step does not lower the residual while
+             * the iterate and the step's end are both within 8 times the
+             * tolerance, the residual sits at the round-off floor of the
+             * arithmetic; the step is taken and the solve stops */
             for (k = 0; k < NL; ++k) trial[k] = lam[k] - d[k];
             equilibrium_and_residual(trial, m, ft, Gt);
-            if (!(norm_2(Gt) < n0) && r <= 8.0 * tol * scale) {
+            if (!(norm_2(Gt) < n0) && r <= 8.0 * tol * scale && norm_inf(Gt) <= 8.0 * tol * scale) {
                 for (k = 0; k < NL; ++k) lam[k] = trial[k];
                 for (k = 0; k < NQ; ++k) feq[k] = ft[k];
                 return it + 1;

@@ -235,10 +235,16 @@ __device__ __forceinline__ int solve_multipliers(const C u[3], C T, C lam[kM], C
 #pragma unroll
         for (int k = 0; k < kM; ++k) n2 += G[k] * G[k];
         n2 = dsqrt(n2);
-        // the full step does not lower the residual while the accepted
-        // iterate is within 8 times the bound: the residual sits at the
-        // round-off floor; the step is taken and the solve stops
-        floor_stop = !fresh && !(n2 < n0) && ls == 0 && near;
+        C r = C(0);
+#pragma unroll
+        for (int k = 0; k < kM; ++k) {
+            const C g = fabs(G[k]);
+            r = (g <= r) ? r : g;  // NaN propagates
+        }
+        // the full step does not lower the residual, but the accepted iterate
+        // and the step's end are both within 8 times the bound: the residual
+        // sits at the round-off floor; the step is taken and the solve stops
+        floor_stop = !fresh && !(n2 < n0) && ls == 0 && near && r <= C(8) * bound;
         if (!fresh && !(n2 < n0) && ls < 39 && !floor_stop) {
             t *= C(0.5);
             ++ls;
@@ -248,12 +254,6 @@ __device__ __forceinline__ int solve_multipliers(const C u[3], C T, C lam[kM], C
         }
         if (!fresh) ++it;
         fresh = false;
-        C r = C(0);
-#pragma unroll
-        for (int k = 0; k < kM; ++k) {
-            const C g = fabs(G[k]);
-            r = (g <= r) ? r : g;  // NaN propagates
-        }
         // residuals of the collision invariants at the accepted iterate:
         // mass, momentum, and sum_i f_i |xi_i|^2 (trace of the second moment)
         resid[0] = G[0];
