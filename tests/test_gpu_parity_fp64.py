@@ -152,7 +152,7 @@ def test_sod_trajectory(orc, lbm, periodic):
 def test_tgv32_single_steps_from_oracle_snapshots(orc, lbm):
     """Config: compressible Taylor-Green vortex, Ma 0.5, Re 1600 (tau from the
     model viscosity), 32^3 copy.  Binding parity: one GPU step from oracle
-    snapshots at several times."""
+    snapshots at several times up to the end of the 1000-step run."""
     n = 32
     gamma, T0, ma = 1.4, 0.5, 0.5
     U = ma * np.sqrt(gamma * T0)
@@ -165,7 +165,7 @@ def test_tgv32_single_steps_from_oracle_snapshots(orc, lbm):
     o = orc.Oracle(n, n, n, gamma=gamma, tau=tau, kn_relax=True, newton_tol=1e-13, newton_maxit=30)
     assert o.init(*fields) == 0
     done = 0
-    for snap in (0, 5, 20):
+    for snap in (0, 5, 20, 100, 500, 999):
         o.step(snap - done)
         done = snap
         s0.set_state(o.f, o.g, o.lam)
@@ -502,4 +502,36 @@ def test_diagnostics_of_cells_without_equilibrium(orc, lbm):
     s.set_state(f, G.reshape(-1), lam)
     eps, its = _diag_compare(o, s, shape, eps_values=False)
     assert np.isnan(eps).sum() > 0 and np.all(its[np.isnan(eps)] == 30)
+    s.close()
+
+
+def test_tgv32_trajectory_at_roundoff_floor(orc, lbm):
+    """Config: the 32^3 TGV copy run for 1000 steps on both sides.  The
+    under-resolved flow amplifies rounding differences, so the bar is the
+    measured floor: the same oracle built with FMA contraction against the
+    plain build, times 20 (and never below 1e-10)."""
+    n = 32
+    gamma, T0, ma = 1.4, 0.5, 0.5
+    U = ma * np.sqrt(gamma * T0)
+    fields = inputs.taylor_green_fields(n, U, T0)
+    kw = dict(gamma=gamma, mach=ma, reynolds=1600.0, length_ref=n / (2 * np.pi), T_ref=T0, u_dir=(1, 0, 0),
+              kn_relax=True, newton_tol=1e-13, newton_maxit=30)
+    s = lbm.Solver((n, n, n), fields=fields, storage="fp64", **kw)
+    tau = s.info().tau
+    okw = dict(gamma=gamma, tau=tau, kn_relax=True, newton_tol=1e-13, newton_maxit=30)
+    o = orc.Oracle(n, n, n, **okw)
+    o2 = orc.Oracle(n, n, n, variant="fma", **okw)
+    assert o.init(*fields) == 0 and o2.init(*fields) == 0
+    for k in range(4):
+        o.step(250)
+        o2.step(250)
+        s.step(250)
+        m, t = s.moments()
+        mo, to = o.moments()
+        m2, _ = o2.moments()
+        err = max(moment_error(m, mo))
+        floor = max(moment_error(m2, mo))
+        _log(f"  step {250 * (k + 1)}: gpu-oracle {err:.2e}, oracle-fma floor {floor:.2e}")
+        assert err <= max(1e-10, 20 * floor), (k, err, floor)
+        assert abs(t[0] - to[0]) < 1e-12 * to[0]
     s.close()
