@@ -709,7 +709,11 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f32(const SlotTa
         uint64_t links = 0;
         if (fluid && d.has_links) links = d.links[cell];
         if (links >> 63) fluid = false;  // solid cells pass through unchanged
+        // the memory phase (row stores, then the next gather) issues ahead of
+        // the other waves' arithmetic
+        __builtin_amdgcn_s_setprio(1);
         if (in_grid) f32::gather(d, srcb, x, y, z, cell, links, !fluid, rows);
+        __builtin_amdgcn_s_setprio(0);
         f32::wait_vmem();
         int32_t it_cell = 0;
         if (fluid) {
@@ -723,6 +727,7 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f32(const SlotTa
             acc[9] += lane == 0 ? 1 : 0;
         }
         // store the wave's rows
+        __builtin_amdgcn_s_setprio(1);
         const uint64_t nS64 = (uint64_t)d.n * 4;
         const float *col = park + wave * kSegment;
         if (full) {
@@ -802,7 +807,11 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f16(const SlotTa
         uint64_t links = 0;
         if (fluid && d.has_links) links = d.links[cell];
         if (links >> 63) fluid = false;  // solid cells pass through unchanged
+        // the memory phase (row stores, then the next gather) issues ahead of
+        // the other waves' arithmetic
+        __builtin_amdgcn_s_setprio(1);
         if (in_grid) f32::gather<2>(d, srcb, x, y, z, cell, links, !fluid, rows);
+        __builtin_amdgcn_s_setprio(0);
         f32::wait_vmem();
         int32_t it_cell = 0;
         if (fluid) {
@@ -817,6 +826,7 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f16(const SlotTa
             acc[9] += lane == 0 ? 1 : 0;
         }
         // store the wave's rows
+        __builtin_amdgcn_s_setprio(1);
         const uint64_t nS64 = (uint64_t)d.n * 2;
         const uint32_t *col = park + wave * kSegment;
         if (full) {
@@ -1076,7 +1086,11 @@ __global__ __launch_bounds__(kBlockThreads, 1) void step_kernel_f64(const SlotTa
         uint64_t links = 0;
         if (fluid && d.has_links) links = d.links[cell];
         if (links >> 63) fluid = false;  // solid cells pass through unchanged
+        // the memory phase (row stores, then the next gather) issues ahead of
+        // the other waves' arithmetic
+        __builtin_amdgcn_s_setprio(1);
         if (in_grid) f64::gather(d, srcb, x, y, z, cell, links, !fluid, rows);
+        __builtin_amdgcn_s_setprio(0);
         f32::wait_vmem();
         int32_t it_cell = 0;
         if (fluid) {
@@ -1090,6 +1104,7 @@ __global__ __launch_bounds__(kBlockThreads, 1) void step_kernel_f64(const SlotTa
             acc[9] += lane == 0 ? 1 : 0;
         }
         // store the wave's rows
+        __builtin_amdgcn_s_setprio(1);
         const uint64_t nS64 = (uint64_t)d.n * 8;
         if (full) {
             // lanes 32r..32r+31 store row i0 + r, two cells each
