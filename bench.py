@@ -166,7 +166,11 @@ def serving_leg(count, rate, seed=2024, arena_gib=96, max_slots=64, graph_steps=
     # warm the graph and the admission path once (untimed)
     warm = inputs.serving_trace(seed + 1, 2, 1e6, tube_cells=(200, 400), box_cells=(16, 16), steps=(40, 40))
     serve.serve_batched(warm, pool, realtime=False)
-    _, batched = serve.serve_batched(trace, pool)
+    def progress(o, name):
+        if o.rid % 20 == 19:
+            print(f"# serving {name}: request {o.rid + 1} done at {o.done:.1f} s", file=sys.stderr, flush=True)
+
+    _, batched = serve.serve_batched(trace, pool, progress=lambda o: progress(o, "batched"))
     pool.close()
     del pool
     torch.cuda.empty_cache()
@@ -176,7 +180,7 @@ def serving_leg(count, rate, seed=2024, arena_gib=96, max_slots=64, graph_steps=
            "pool": {"arena_gib": arena_gib, "max_slots": max_slots, "graph_steps": graph_steps, "sched": sched},
            "batched": batched}
     if sequential:
-        _, seq = serve.serve_sequential(trace, storage="fp32s")
+        _, seq = serve.serve_sequential(trace, storage="fp32s", progress=lambda o: progress(o, "one at a time"))
         print(f"# serving one-at-a-time: p50 {seq['p50_s']:.3f} s p99 {seq['p99_s']:.3f} s "
               f"{seq['aggregate_glups']:.3f} GLUPS", file=sys.stderr, flush=True)
         out["one_at_a_time"] = seq

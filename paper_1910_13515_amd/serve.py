@@ -180,7 +180,7 @@ def _cells(req):
     return req.shape[0] * req.shape[1] * req.shape[2]
 
 
-def serve_batched(trace, pool, keep_fields: bool = False, realtime: bool = True):
+def serve_batched(trace, pool, keep_fields: bool = False, realtime: bool = True, progress=None):
     """Continuous batching over a pool.  With realtime, requests become
     visible at their arrival times (relative to the start); otherwise all are
     visible at once.  Arrivals are admitted in arrival order as soon as their
@@ -203,6 +203,8 @@ def serve_batched(trace, pool, keep_fields: bool = False, realtime: bool = True)
             o.done = now()
             o.totals, o.fields = tot, f
             pool.release(slot)
+            if progress:
+                progress(o)
 
     while pending or waiting or active:
         t = now()
@@ -240,7 +242,8 @@ def serve_batched(trace, pool, keep_fields: bool = False, realtime: bool = True)
     return outs, summarize(outs, t_first, t_last)
 
 
-def serve_sequential(trace, storage: str = "fp32s", keep_fields: bool = False, realtime: bool = True):
+def serve_sequential(trace, storage: str = "fp32s", keep_fields: bool = False, realtime: bool = True,
+                     progress=None):
     """The same trace, one solve at a time with the plain calls."""
     pending = sorted(trace, key=lambda r: r.arrival)
     outcomes = []
@@ -260,6 +263,8 @@ def serve_sequential(trace, storage: str = "fp32s", keep_fields: bool = False, r
         o.totals, o.fields = tot, f
         s.close()
         outcomes.append(o)
+        if progress:
+            progress(o)
     by_id = {o.rid: o for o in outcomes}
     outs = [by_id[r.rid] for r in trace]
     t_first = min(o.arrival for o in outs)
