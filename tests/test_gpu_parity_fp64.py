@@ -372,6 +372,60 @@ def test_full_size_airfoil_step(orc, lbm):
     s.close()
 
 
+def _crop(a, shape, box):
+    """Cells of the box (x0, x1, y0, y1, z0, z1) of a field laid out x fastest
+    (the last axis of a may be the cells; leading axes are kept)."""
+    nx, ny, nz = shape
+    x0, x1, y0, y1, z0, z1 = box
+    lead = a.shape[:-1]
+    v = a.reshape(lead + (nz, ny, nx))[..., z0:z1, y0:y1, x0:x1]
+    return np.ascontiguousarray(v).reshape(lead + (-1,))
+
+
+def test_full_size_sphere_steps(orc, lbm):
+    """The supersonic sphere at its full size (512 x 256 x 256, radius 24 at
+    x = 128, Ma 1.5, equilibrium and Neumann faces): three GPU steps from the
+    free stream on the whole grid against the oracle on an 84 x 72 x 72 box
+    around the sphere.  A step pulls from at most three cells away, so after
+    three steps every cell nine or more cells inside the box depends on the
+    box alone; those cells (including the whole sphere surface) are compared
+    at 1e-12."""
+    from paper_1910_13515_amd import precision_study as ps
+    shape, solid, kw = ps.sphere_case(1.0)
+    kw = dict(kw, newton_tol=1e-13, newton_maxit=30)
+    s = lbm.Solver(shape, solid=solid, storage="fp64", **kw)
+    info = s.info()
+    k = 3
+    st, code = lbm.lbm_step(s.ctx, k, with_stats=True)
+    assert code == lbm.LBM_OK and st.failed == 0
+    m, _ = s.moments()
+    box = (92, 176, 92, 164, 92, 164)
+    cshape = (box[1] - box[0], box[3] - box[2], box[5] - box[4])
+    csolid = _crop(solid, shape, box)
+    _log(f"sphere tau={info.tau:.6f} fluid={info.fluid_cells}; oracle box {cshape}, solid {int(csolid.sum())}")
+    o = orc.Oracle(*cshape, gamma=kw["gamma"], tau=info.tau, kn_relax=True, solid=csolid, newton_tol=1e-13,
+                   newton_maxit=30)
+    nc = int(np.prod(cshape))
+    u = np.zeros((3, nc))
+    u[0] = info.u_ref[0]
+    assert o.init(np.ones(nc), u, np.full(nc, kw["T_ref"])) == 0
+    o.step(k)
+    mo, _ = o.moments()
+    r = 3 * k
+    inner = (r, cshape[0] - r, r, cshape[1] - r, r, cshape[2] - r)
+    mg = _crop(_crop(m, shape, box), cshape, inner)
+    mo = _crop(mo, cshape, inner)
+    fluid = np.isfinite(mo[0])
+    # the comparison reaches every solid cell's fluid neighbours
+    assert _crop(csolid, cshape, inner).sum() == csolid.sum()
+    em = moment_error(mg[:, fluid], mo[:, fluid])
+    moved = np.abs(mo[1][fluid] - info.u_ref[0]).max()
+    _log(f"sphere: {int(fluid.sum())} cells compared, moments rho/u/T {em}, max change of u_x {moved:.2e}")
+    assert moved > 1e-3  # the sphere has disturbed the compared region
+    assert max(em) <= TOL
+    s.close()
+
+
 @pytest.mark.parametrize("shape", [(1, 1, 1), (1, 7, 3), (5, 1, 1), (64, 1, 2), (65, 2, 1), (256, 2, 2)])
 def test_degenerate_and_segment_edge_grids(orc, lbm, shape):
     """Grids where every velocity wraps onto few cells (1x1x1, single-cell

@@ -181,6 +181,88 @@ def test_full_size_tgv128_step(orc, lbm, storage):
     s.close()
 
 
+def _crop(a, shape, box):
+    nx, ny, nz = shape
+    x0, x1, y0, y1, z0, z1 = box
+    lead = a.shape[:-1]
+    v = a.reshape(lead + (nz, ny, nx))[..., z0:z1, y0:y1, x0:x1]
+    return np.ascontiguousarray(v).reshape(lead + (-1,))
+
+
+@pytest.mark.parametrize("storage", ["fp32s", "fp16s"])
+def test_full_size_sphere_step(orc, lbm, storage):
+    """The sphere flow at its full size (512 x 256 x 256): one reduced-precision
+    GPU step from the free stream on the whole grid against one oracle step on
+    a 60 x 56 x 56 box around the sphere; cells three or more inside the box
+    depend on the box alone and are compared at the single-step moment bar."""
+    from paper_1910_13515_amd import precision_study as ps
+    shape, solid, kw = ps.sphere_case(1.0)
+    s = lbm.Solver(shape, solid=solid, storage=storage, **kw)
+    info = s.info()
+    st, code = lbm.lbm_step(s.ctx, 1, with_stats=True)
+    assert code == lbm.LBM_OK and st.failed == 0
+    m, _ = s.moments()
+    box = (98, 158, 100, 156, 100, 156)
+    cshape = (box[1] - box[0], box[3] - box[2], box[5] - box[4])
+    csolid = _crop(solid, shape, box)
+    o = orc.Oracle(*cshape, gamma=kw["gamma"], tau=info.tau, kn_relax=True, solid=csolid, newton_tol=1e-13,
+                   newton_maxit=30)
+    nc = int(np.prod(cshape))
+    u = np.zeros((3, nc))
+    u[0] = info.u_ref[0]
+    assert o.init(np.ones(nc), u, np.full(nc, kw["T_ref"])) == 0
+    f_in, g_in = o.stream_only(o.f), o.stream_only(o.g)  # what the step gathers
+    o.step(1)
+    mo, _ = o.moments()
+    inner = (3, cshape[0] - 3, 3, cshape[1] - 3, 3, cshape[2] - 3)
+    assert _crop(csolid, cshape, inner).sum() == csolid.sum()
+    mg = _crop(_crop(m, shape, box), cshape, inner)
+    mo = _crop(mo, cshape, inner)
+    fluid = np.isfinite(mo[0])
+    em = moment_error(mg[:, fluid], mo[:, fluid])
+    _log(f"{storage} sphere: {int(fluid.sum())} cells compared, moments rho/u/T {em}")
+    if storage == "fp32s":
+        assert max(em) < BARS[storage][1]
+    else:
+        # The supersonic free stream sits far from the rest weights, so the
+        # deviations FP16 stores are large.  A stored population is off by at
+        # most 2^-11 of its deviation d_i = h_i - w_i from the rest weight:
+        # once in what the step gathers and once in what it writes, while the
+        # collision itself conserves mass, momentum and energy (to FP32
+        # rounding, 1e-5 here).  Per cell, with D = sum of both deviations:
+        #   |d rho| <= 2^-11 D(1),  |d j| <= 2^-11 D(|xi|),
+        #   |d E| <= 2^-11 (D_f(|xi|^2) + D_g(1)),
+        # carried into u = j / rho and T = (E - rho |u|^2) / (2 C_v rho) to
+        # first order.
+        xi = orc.velocities().astype(np.float64)
+        q = (xi ** 2).sum(1)
+        wf, wg, _, _ = orc.equilibrium(1.0, [0.0, 0.0, 0.0], kw["T_ref"], gamma=kw["gamma"])
+
+        def dev(h, w):
+            return np.abs(_crop(h.reshape(39, nc), cshape, inner)[:, fluid] - w[:, None])
+
+        df = dev(f_in, wf) + dev(o.f, wf)
+        dg = dev(g_in, wg) + dev(o.g, wg)
+        u16 = 2.0 ** -11
+        rho, u, T = mo[0, fluid], mo[1:4, fluid], mo[4, fluid]
+        speed = np.sqrt((u ** 2).sum(0))
+        b_rho = u16 * df.sum(0) + 1e-5 * rho
+        b_j = u16 * (df * np.sqrt(q)[:, None]).sum(0) + 1e-5 * rho
+        two_cv = 2.0 / (kw["gamma"] - 1.0)
+        b_e = u16 * ((df * q[:, None]).sum(0) + dg.sum(0)) + 1e-5 * rho * (speed ** 2 + two_cv * T)
+        b_u = (b_j + speed * b_rho) / rho
+        # 2 C_v (T d rho + rho dT) = dE - 2 u . dj + |u|^2 d rho
+        b_T = (b_e + 2.0 * speed * b_j + (speed ** 2 + two_cv * T) * b_rho) / (two_cv * rho)
+        e_rho = np.abs(mg[0, fluid] - rho)
+        e_u = np.sqrt(((mg[1:4, fluid] - u) ** 2).sum(0))
+        e_T = np.abs(mg[4, fluid] - T)
+        worst = max((e_rho / b_rho).max(), (e_u / b_u).max(), (e_T / b_T).max())
+        _log(f"fp16s sphere: largest error / bound {worst:.3f} (rho {(e_rho / b_rho).max():.3f}, "
+             f"u {(e_u / b_u).max():.3f}, T {(e_T / b_T).max():.3f}); bound on rho up to {(b_rho / rho).max():.2e}")
+        assert worst <= 1.0
+    s.close()
+
+
 @pytest.mark.parametrize("storage", ["fp32s", "fp16s"])
 def test_supersonic_airfoil_stays_stable(lbm, storage):
     """The Ma 1.5 NACA0012 flow at half size (1024 x 512, chord 128): the
