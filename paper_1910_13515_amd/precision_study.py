@@ -71,9 +71,13 @@ CASES = {"airfoil": (airfoil_case, ("fp64", "fp32s"), 20000),
 
 
 def run(shape, solid, kw, storage, steps, chunk=1000, log=None):
-    """Runs one mode; returns (fields[5, N], summary)."""
+    """Runs one mode; returns (fields[5, N], summary).  A mode "fp16s@stream"
+    (or "fp32s@stream") stores deviations from the free stream's equilibrium
+    instead of the rest weights (shift_ref = 1)."""
     import torch
-    s = lbm.Solver(shape, solid=solid, storage=storage, **kw)
+    mode = storage
+    storage, _, ref = mode.partition("@")
+    s = lbm.Solver(shape, solid=solid, storage=storage, shift_ref=int(ref == "stream"), **kw)
     info = s.info()
     t0 = time.perf_counter()
     failed = 0
@@ -84,7 +88,7 @@ def run(shape, solid, kw, storage, steps, chunk=1000, log=None):
         failed += st.failed
         done += k
         if log:
-            log(f"{storage}: {done}/{steps} steps, Newton failures so far {failed}")
+            log(f"{mode}: {done}/{steps} steps, Newton failures so far {failed}")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = s.step(1, stats=True)  # statistics of one further step
@@ -95,7 +99,7 @@ def run(shape, solid, kw, storage, steps, chunk=1000, log=None):
     torch.cuda.empty_cache()
     upd = max(1, st.cell_updates)
     return fields, {
-        "storage": storage, "tau": info.tau, "seconds": dt, "glups": info.cells * steps / dt / 1e9,
+        "storage": storage, "shift": "free stream" if ref == "stream" else "rest weights", "tau": info.tau, "seconds": dt, "glups": info.cells * steps / dt / 1e9,
         "newton_failures": int(failed), "newton_iterations_per_cell": st.iterations / upd,
         "newton_max_iterations": int(st.max_iterations),
         "alpha_fraction": [a / upd for a in st.alpha_hist], "totals": [float(v) for v in tot],
@@ -143,7 +147,9 @@ def main():
     ap.add_argument("--case", choices=sorted(CASES), required=True)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--scale", type=float, default=1.0)
-    ap.add_argument("--modes", default=None, help="comma-separated subset of fp64,fp32s,fp16s")
+    ap.add_argument("--modes", default=None,
+                    help="comma-separated subset of fp64,fp32s,fp16s; fp32s@stream and fp16s@stream shift the "
+                         "stored deviations by the free stream's equilibrium")
     ap.add_argument("--mach", type=float, default=1.5)
     args = ap.parse_args()
     import torch

@@ -131,6 +131,52 @@ def test_cells_without_equilibrium_keep_their_state(orc, lbm, storage):
 
 
 @pytest.mark.parametrize("storage", ["fp32s", "fp16s"])
+def test_stream_shift_single_step(orc, lbm, storage):
+    """Storage shifted by the equilibrium of a Mach 1.2 stream (shift_ref = 1)
+    on a periodic grid: one step from a random state around that stream
+    against the oracle, at the single-step bars.  On such states the stream
+    shift stores small deviations, so for FP16 it is more accurate than the
+    rest-weight shift.  Plain BGK (no alpha(eps)): the storage is the subject,
+    not the relaxation branch, whose thresholds these states sit near."""
+    shape = (70, 5, 4)
+    gamma, T0, ma = 1.4, 0.5, 1.2
+    U = ma * np.sqrt(gamma * T0)
+    rho, u, T = inputs.random_fields(shape, seed=53, rho=(0.95, 1.05), umax=0.05, T=(0.48, 0.52))
+    u[0] += U
+    o0 = orc.Oracle(*shape, gamma=gamma)
+    assert o0.init(rho, u, T) == 0
+    pert = inputs.random_perturbation(shape, seed=54, amplitudes=(1e-3, 1e-2))
+    f = o0.f * np.exp(pert[0].reshape(-1))
+    g = o0.g * np.exp(pert[1].reshape(-1))
+    lam = o0.lam.copy()
+    o = orc.Oracle(*shape, gamma=gamma, tau=0.55, kn_relax=False, newton_tol=1e-13)
+    o.set_state(f, g, lam)
+    o.step(1)
+    mo, _ = o.moments()
+    errs = {}
+    for shift in (0, 1):
+        s = lbm.Solver(shape, storage=storage, gamma=gamma, tau=0.55, kn_relax=False, mach=ma, T_ref=T0,
+                       u_dir=(1, 0, 0), shift_ref=shift)
+        s.set_state(f, g, lam)
+        st = s.step(1, stats=True)
+        fg, gg, _ = s.get_state()
+        m, _ = s.moments()
+        errs[shift] = (max_rel(fg, o.f), max_rel(gg, o.g), max(moment_error(m, mo)), int(st.failed))
+        s.close()
+    _log(f"{storage} around a Ma {ma} stream: (f, g, moments, failed) rest shift {errs[0]}, stream shift {errs[1]}")
+    bar_pop, bar_mom, _ = BARS[storage]
+    # the Newton solve stops at tol * max(1, max_k |m_k|); around this stream
+    # the largest target, the contracted third moment |u| (|u|^2 + 5 T), is
+    # about 3.5, and the populations' bar grows with it
+    speed = np.sqrt((mo[1:4] ** 2).sum(0))
+    bar_pop *= max(1.0, float((speed * (speed ** 2 + 5.0 * mo[4])).max()))
+    ef, eg, em, failed = errs[1]
+    assert failed == 0 and ef < bar_pop and eg < bar_pop and em < bar_mom
+    if storage == "fp16s":
+        assert max(errs[1][:3]) < max(errs[0][:3])
+
+
+@pytest.mark.parametrize("storage", ["fp32s", "fp16s"])
 def test_full_size_tgv128_step(orc, lbm, storage):
     """The benchmark's workload at full size (128^3 TGV): one reduced-precision
     GPU step from the oracle's state after one step, against the oracle's
