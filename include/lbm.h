@@ -72,9 +72,9 @@ typedef struct {
     int32_t nx, ny, nz;        /* cells (>= 1; a non-periodic axis needs >= 7) */
     int32_t storage;           /* lbm_storage */
     int32_t shift_ref;         /* shifted storage only: 0 = rest-state equilibrium at (rho_ref, T_ref),
-                                  1 = equilibrium of the reference stream (rho_ref, u_ref, T_ref); 1 with a
-                                  solid mask is LBM_E_INVAL (bounce-back needs equal weights of opposite
-                                  velocities) */
+                                  1 = equilibrium of the reference stream (rho_ref, u_ref, T_ref); with 1
+                                  opposite velocities have unequal weights, and a bounce-back moves the
+                                  gathered deviation onto the other weight (FP16: one more rounding) */
     int32_t kn_relax;          /* 1: tau(eps) = tau * alpha(eps), Eq. (eq:alpha); 0: plain BGK */
     int32_t newton_maxit;      /* cap on Newton updates per cell and step (0: 20) */
     int32_t faces[6];          /* lbm_face for -x, +x, -y, +y, -z, +z */

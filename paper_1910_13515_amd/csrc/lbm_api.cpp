@@ -82,11 +82,6 @@ std::string validate(const lbm_params *p)
     // the FP16 row stores reach 8 planes (of 2n bytes) from one 32-bit lane offset
     if (p->storage == LBM_STORE_FP16_SHIFTED && 8 * n * 2 >= ((int64_t)1 << 32)) return "grid too large for FP16 storage";
     if (p->shift_ref < 0 || p->shift_ref > 1) return "shift_ref must be 0 or 1";
-    // half-way bounce-back hands a stored deviation to the opposite velocity,
-    // which is the population itself only when the two shift weights agree:
-    // true of the rest weights, not of a moving stream's equilibrium
-    if (p->shift_ref == 1 && p->storage != LBM_STORE_FP64 && p->solid != nullptr)
-        return "shift_ref = 1 cannot be combined with a solid mask (bounce-back needs symmetric shift weights)";
     const int dims[3] = {p->nx, p->ny, p->nz};
     for (int a = 0; a < 3; ++a) {
         const int lo = p->faces[2 * a], hi = p->faces[2 * a + 1];
@@ -408,6 +403,14 @@ int lbm_create(const lbm_params *params, void *dev_arena, int64_t arena_bytes, v
             mom[1] += wf * cy;
             mom[2] += wf * cz;
             ener += wf * (cx * cx + cy * cy + cz * cz) + wg;
+        }
+        // bounce-back correction for unequal weights of opposite velocities
+        // (the weights lie on a 2^-21 grid, so the differences are exact)
+        d.asym_bounce = 0;
+        for (int i = 0; i < 2 * kQ; ++i) {
+            const int v = i % kQ, o = (i < kQ ? 0 : kQ) + opposite(v);
+            d.bb_corr[i] = d.shift_w[o] - d.shift_w[i];
+            if (d.bb_corr[i] != 0.0f && d.has_links) d.asym_bounce = 1;
         }
         d.ref_mass = (float)mass;
         d.ref_mom[0] = (float)mom[0];

@@ -178,6 +178,17 @@ __device__ __forceinline__ void gather_pair(const SlotDesc &d, gcbyte *srcb, uin
         ga *= sg;
         gb *= sg;
     }
+    if constexpr (StoreTraits<S>::kShift) {
+        // a blocked link gathered the opposite velocity's deviation: move it
+        // onto this velocity's shift weight (zero for symmetric weights)
+        if (d.asym_bounce) {
+            const bool ba = (links >> a) & 1ull, bb = (links >> b) & 1ull;
+            fa = ba ? fa + C(d.bb_corr[a]) : fa;
+            ga = ba ? ga + C(d.bb_corr[kQ + a]) : ga;
+            fb = bb ? fb + C(d.bb_corr[b]) : fb;
+            gb = bb ? gb + C(d.bb_corr[kQ + b]) : gb;
+        }
+    }
     pk.put(a, fa);
     pk.put(b, fb);
     pk.put(kQ + a, ga);
@@ -588,6 +599,22 @@ struct ParkHalf {
     }
 };
 
+// Blocked links of a cell whose opposite velocities have unequal shift
+// weights: the gather brought the opposite velocity's stored deviation, which
+// moves onto this velocity's weight here (FP16: re-encoded in its shell scale,
+// which opposite velocities share)
+template <class PK>
+__device__ __forceinline__ void bounce_fix(const SlotDesc &d, const PK &pk, uint64_t links)
+{
+#pragma unroll
+    for (int i = 1; i < kQ; ++i) {
+        if ((links >> i) & 1ull) {
+            pk.put(i, pk.get(i) + d.bb_corr[i]);
+            pk.put(kQ + i, pk.get(kQ + i) + d.bb_corr[kQ + i]);
+        }
+    }
+}
+
 // moments, Newton, sensor and relaxation of one fluid cell whose gathered
 // values sit in LDS; the results replace them
 template <class PK>
@@ -717,6 +744,7 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f32(const SlotTa
         f32::wait_vmem();
         int32_t it_cell = 0;
         if (fluid) {
+            if (d.asym_bounce && links) f32::bounce_fix(d, pk, links);
             const int32_t before = acc[0];
             f32::collide(d, cell, pk, acc);
             it_cell = acc[0] - before;
@@ -816,6 +844,7 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f16(const SlotTa
         int32_t it_cell = 0;
         if (fluid) {
             const f32::ParkHalf pk{park + threadIdx.x, &d.shell_scale[0][0], &d.shell_inv_scale[0][0]};
+            if (d.asym_bounce && links) f32::bounce_fix(d, pk, links);
             const int32_t before = acc[0];
             f32::collide(d, cell, pk, acc);
             it_cell = acc[0] - before;

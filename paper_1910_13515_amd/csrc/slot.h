@@ -57,6 +57,12 @@ struct SlotDesc {
     float proj_w[6];
     float proj_inv[3];
     float proj_inv_w2;
+    // shifted storage with unequal shift weights of opposite velocities
+    // (a stream-shifted solve with obstacles): a half-way bounce-back gathers
+    // the stored deviation of the opposite velocity, which becomes the
+    // population once bb_corr[i] = w_opp(i) - w_i is added (f: 0..38, g: 39..77)
+    int32_t asym_bounce;
+    float bb_corr[78];
 };
 
 struct SlotTable {

@@ -67,7 +67,7 @@ def sphere_case(scale: float = 1.0, mach: float = 1.5):
 
 
 CASES = {"airfoil": (airfoil_case, ("fp64", "fp32s"), 20000),
-         "sphere": (sphere_case, ("fp64", "fp32s", "fp16s"), 2000)}
+         "sphere": (sphere_case, ("fp64", "fp32s", "fp16s", "fp16s@stream"), 2000)}
 
 
 def run(shape, solid, kw, storage, steps, chunk=1000, log=None):

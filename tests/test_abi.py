@@ -61,25 +61,6 @@ def test_parameter_validation_without_device(L):
     assert b"NULL" in lbm.load().lbm_last_error(None)
 
 
-def test_stream_shift_with_obstacle_is_rejected(L):
-    """Shifted storage around a moving stream's equilibrium has unequal
-    weights for opposite velocities, so bounce-back cannot hand the stored
-    deviation over; such a solve is refused (FP64 has no shift and is not)."""
-    mask = np.zeros(16 * 8, dtype=np.uint8)
-    mask[40] = 1
-    for storage, shift, ok in (("fp32s", 1, False), ("fp16s", 1, False), ("fp32s", 0, True), ("fp64", 1, True)):
-        p = lbm.make_params((16, 8, 1), tau=0.6, mach=0.5, u_dir=(1, 0, 0), storage=storage, shift_ref=shift)
-        p.solid = mask.ctypes.data
-        if ok:
-            assert lbm.lbm_required_bytes(p) > 0
-        else:
-            with pytest.raises(lbm.LbmError) as e:
-                lbm.lbm_required_bytes(p)
-            assert e.value.code == lbm.LBM_E_INVAL
-    p = lbm.make_params((16, 8, 1), tau=0.6, mach=0.5, u_dir=(1, 0, 0), storage="fp16s", shift_ref=1)
-    assert lbm.lbm_required_bytes(p) > 0  # without obstacles the shift is allowed
-
-
 def test_required_bytes_scale_with_storage(L):
     n = 64 * 32 * 16
     b64 = lbm.lbm_required_bytes(lbm.make_params((64, 32, 16), tau=0.6, storage="fp64"))
