@@ -86,7 +86,7 @@ typedef struct {
     double u_dir[3];           /* direction of u_ref (normalised here; zero vector with mach = 0 is allowed) */
     double tau;                /* > 0: relaxation time as given; <= 0: derived from reynolds */
     double newton_tol;         /* stopping bound on max_k |G_k|/rho relative to max(1, max_k |M_k|/rho)
-                                  (0: 1e-12 in FP64 as in Sec. 5, 2e-6 in FP32 arithmetic) */
+                                  (0: 1e-12 in FP64 as in Sec. 5, 1e-5 in FP32 arithmetic) */
     const uint8_t *solid;      /* nx*ny*nz obstacle flags (nonzero = solid) or NULL */
     const double *init_rho;    /* initial fields (N, 3N as ux|uy|uz, N) or NULL for the reference state */
     const double *init_u;

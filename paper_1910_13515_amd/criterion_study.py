@@ -1,0 +1,146 @@
+"""Influence of the Newton solver's convergence threshold on the fused step.
+
+Sec. 6 of the paper names the root finder's convergence criterion as one of
+the method's open parameters.  The criterion here is the solver's stopping
+rule (Sec. 5 table): max_k |G_k| <= tol * max(1, max_k |m_k|).  This sweeps
+tol for the reduced-precision modes and reports, per (mode, tol):
+
+* on the periodic 128^3 Taylor-Green vortex (Ma 0.5, Re 1600): the GLUPS of
+  timed steps, the Newton updates per cell and per wave (a wave runs as many
+  updates as its slowest cell), and the L2 error of (rho, u, T) after the run
+  against the FP64 step at tol 1e-12;
+* on the full-size supersonic airfoil (2048 x 1024, Ma 1.5, Re 1e4): whether
+  the run stays finite, its Newton failures, and its error against FP64.
+
+    python -m paper_1910_13515_amd.criterion_study [--tols 1e-4,1e-5,2e-6,1e-6] [--modes fp32s,fp16s]
+                                                   [--airfoil-steps 20000] [--no-airfoil]
+
+Prints one JSON object.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import inputs, lbm, precision_study
+
+TGV_N = 128
+TGV_WARMUP = 20
+TGV_TIMED = 100
+
+
+def _tgv_setup():
+    gamma, T0, ma = 1.4, 0.5, 0.5
+    U = ma * np.sqrt(gamma * T0)
+    fields = inputs.taylor_green_fields(TGV_N, U, T0)
+    kw = dict(gamma=gamma, mach=ma, reynolds=1600.0, length_ref=TGV_N / (2 * np.pi), T_ref=T0, u_dir=(1, 0, 0),
+              kn_relax=True)
+    return fields, kw
+
+
+def _tgv_run(storage, tol, fields, kw):
+    """Warm-up, timed steps and one statistics step; returns (fields, summary)."""
+    import torch
+    s = lbm.Solver((TGV_N,) * 3, fields=fields, storage=storage, newton_tol=tol, **kw)
+    s.step(TGV_WARMUP)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(TGV_TIMED)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = s.step(1, stats=True)
+    m, _ = s.moments()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    upd = max(1, st.cell_updates)
+    return m, {"glups": TGV_N ** 3 * TGV_TIMED / dt / 1e9, "newton_per_cell": st.iterations / upd,
+               "newton_per_wave": st.wave_iterations / max(1, st.waves), "failed": int(st.failed)}
+
+
+def tgv(modes, tols, log=None):
+    fields, kw = _tgv_setup()
+    ref, summ = _tgv_run("fp64", 1e-12, fields, kw)
+    out = {"workload": f"periodic {TGV_N}^3 Taylor-Green vortex, Ma 0.5, Re 1600",
+           "steps": TGV_WARMUP + TGV_TIMED + 1, "fp64": summ, "runs": []}
+    fluid = np.ones(TGV_N ** 3, dtype=bool)
+    for m in modes:
+        for tol in tols:
+            f, summ = _tgv_run(m, tol, fields, kw)
+            summ.update({"storage": m, "tol": tol, "vs_fp64": precision_study.errors(f, ref, fluid)})
+            if log:
+                log(f"tgv {m} tol {tol:g}: {summ['glups']:.3f} GLUPS, {summ['newton_per_wave']:.2f} updates/wave, "
+                    f"e_rho {summ['vs_fp64']['l2_rho']:.2e}")
+            out["runs"].append(summ)
+    return out
+
+
+def _airfoil_run(shape, solid, kw, storage, tol, steps, log=None, chunk=1000):
+    """Runs until `steps` or until the totals stop being finite; returns
+    (fields or None, summary)."""
+    import torch
+    s = lbm.Solver(shape, solid=solid, storage=storage, newton_tol=tol, **kw)
+    failed, done, finite = 0, 0, True
+    t0 = time.perf_counter()
+    while done < steps:
+        k = min(chunk, steps - done)
+        st = s.step(k, stats=True)
+        failed += int(st.failed)
+        done += k
+        _, tot = s.moments(fields=False)
+        if not np.all(np.isfinite(tot)):
+            finite = False
+            break
+        if log:
+            log(f"airfoil {storage} tol {tol:g}: {done}/{steps} steps, Newton failures {failed}")
+    dt = time.perf_counter() - t0
+    f = s.moments()[0] if finite else None
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return f, {"storage": storage, "tol": tol, "steps_run": done, "finite": finite, "newton_failures": failed,
+               "seconds": dt}
+
+
+def airfoil(modes, tols, steps, log=None):
+    shape, solid, kw = precision_study.airfoil_case(1.0)
+    fluid = solid.reshape(-1) == 0
+    ref, summ = _airfoil_run(shape, solid, kw, "fp64", 0.0, steps, log)
+    out = {"workload": "NACA0012 2048 x 1024, Ma 1.5, Re 1e4", "steps": steps, "fp64": summ, "runs": []}
+    for m in modes:
+        for tol in tols:
+            f, summ = _airfoil_run(shape, solid, kw, m, tol, steps, log)
+            if f is not None and ref is not None:
+                summ["vs_fp64"] = precision_study.errors(f, ref, fluid)
+            out["runs"].append(summ)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--tols", default="1e-4,1e-5,2e-6,1e-6")
+    ap.add_argument("--modes", default="fp32s,fp16s")
+    ap.add_argument("--airfoil-steps", type=int, default=20000)
+    ap.add_argument("--no-airfoil", action="store_true")
+    args = ap.parse_args()
+    import torch
+    assert torch.cuda.is_available(), "the criterion study needs a GPU"
+    torch.cuda.set_device(0)
+    tols = [float(v) for v in args.tols.split(",")]
+    modes = args.modes.split(",")
+
+    def log(m):
+        print("#", m, file=sys.stderr, flush=True)
+
+    res = {"criterion": "max_k |G_k| <= tol * max(1, max_k |m_k|)", "tgv": tgv(modes, tols, log)}
+    if not args.no_airfoil:
+        res["airfoil"] = airfoil(modes, tols, args.airfoil_steps, log)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -2,7 +2,7 @@
 arithmetic) against the FP64 oracle on the GPU.
 
 The tolerances follow from the arithmetic: FP32 carries 24 significant bits
-(unit round-off 6e-8) and its Newton solve stops at 2e-6 of the largest
+(unit round-off 6e-8) and its Newton solve stops at 1e-5 of the largest
 target moment; FP16 deviations carry 11 bits (4.9e-4 relative to the
 deviation from the shift weights).  Each test prints its measured errors."""
 import sys
