@@ -34,9 +34,27 @@ __device__ __forceinline__ float dsqrt<float>(float x) { return sqrtf(x); }
 
 // 1/sqrt(x) and 1/x: exact division in FP64; the hardware approximations
 // (about 1 ulp) in the FP32 path.
-__device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
+// FP64: the hardware estimates refined by two Newton steps each (each step
+// squares the relative error), in place of the full-precision division and
+// square-root sequences; used for the Cholesky pivots and the sensor, whose
+// results need accuracy to a few ulp, not correct rounding
+__device__ __forceinline__ double rsqrt_(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double e = __builtin_fma(-(x * y), y, 1.0);  // 1 - x y^2
+    y = __builtin_fma(0.5 * y, e, y);
+    e = __builtin_fma(-(x * y), y, 1.0);
+    return __builtin_fma(0.5 * y, e, y);
+}
 __device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ double recip(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, y, 1.0);  // 1 - x y
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-x, y, 1.0);
+    return __builtin_fma(y, e, y);
+}
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Maxwell-Boltzmann targets per unit density (Eq. eq:EqMomentsTensor, the 13
