@@ -1,0 +1,63 @@
+"""Host-side statistics of the study tools (no GPU): the airfoil's sensor and
+iteration summary, and the error norms of the precision studies."""
+import numpy as np
+
+from paper_1910_13515_amd import knudsen_map, precision_study
+
+
+def _fields(shape, solid):
+    """A synthetic sensor/iteration field with a known composition: frozen
+    face columns (x < 3 or x >= nx - 3, iterations -1), one failed cell, and
+    eps/iterations set by the x coordinate."""
+    nx, ny, _ = shape
+    n = nx * ny
+    x = np.arange(n) % nx
+    eps = np.where(x < nx // 2, 1e-6, 0.05)
+    eps = np.where(x >= nx - nx // 8, 0.5, eps)
+    iters = np.where(x < nx // 2, 0.0, 2.0)
+    frozen = (x < 3) | (x >= nx - 3)
+    iters[frozen] = -1.0
+    eps[frozen] = np.nan
+    sol = solid.reshape(-1) != 0
+    iters[sol] = -1.0
+    eps[sol] = np.nan
+    failed = np.flatnonzero(~frozen & ~sol)[7]
+    eps[failed] = np.nan
+    iters[failed] = 20.0
+    return eps, iters, frozen, sol, failed, x
+
+
+def test_knudsen_summary_counts():
+    shape, solid, _ = precision_study.airfoil_case(0.125)
+    eps, iters, frozen, sol, failed, x = _fields(shape, solid)
+    res = knudsen_map.summarize(shape, solid, eps, iters)
+    upd = ~frozen & ~sol
+    assert res["updated_cells"] == int(upd.sum())
+    nu = res["newton_updates"]
+    assert nu["cells_without_equilibrium"] == 1
+    ok = upd.copy()
+    ok[failed] = False
+    zero = ok & (x < shape[0] // 2)
+    assert nu["histogram_0_to_4_and_more"][0] == int(zero.sum())
+    assert nu["histogram_0_to_4_and_more"][2] == int((ok & ~zero).sum())
+    assert nu["max"] == 2
+    assert abs(nu["share_zero"] - zero.sum() / ok.sum()) < 1e-12
+    shares = res["alpha_branch_share"]
+    assert abs(sum(shares) - 1.0) < 1e-12
+    b2 = ok & (x >= shape[0] - shape[0] // 8)
+    assert abs(shares[2] - b2.sum() / ok.sum()) < 1e-12
+    assert shares[3] == 0.0
+    xr = res["sensor"]["active_x_range"]
+    assert xr[0] == shape[0] // 2 and xr[1] == shape[0] - 4
+
+
+def test_relative_l2_errors():
+    rng = np.random.default_rng(3)
+    ref = rng.uniform(0.5, 1.5, (5, 100))
+    f = ref.copy()
+    f[0] *= 1.0 + 1e-3
+    fluid = np.ones(100, dtype=bool)
+    e = precision_study.errors(f, ref, fluid)
+    assert abs(e["l2_rho"] - 1e-3) < 1e-12
+    assert e["l2_u"] == 0.0 and e["l2_T"] == 0.0
+    assert abs(e["max_rho"] - np.max(np.abs(ref[0]) * 1e-3)) < 1e-15
