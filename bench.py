@@ -209,6 +209,78 @@ def cpu_baseline(seconds_target=15.0):
             "sample": f"FP64 oracle, TGV {n}^3 Ma 0.5 Re 1600, {steps} steps from the initial state, {dt:.1f} s"}
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_table(single_thread=False, log=None):
+    """The FP64 oracle timed on the configurations of the method's workloads
+    (bounded step counts; full runs would take hours on the host).  Uses the
+    OpenMP threads the process was started with (OMP_NUM_THREADS)."""
+    import numpy as np
+
+    import oracle
+    from paper_1910_13515_amd import inputs, precision_study
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    eq, neu = oracle.FACE_EQUILIBRIUM, oracle.FACE_NEUMANN
+
+    def timed(name, shape, fields, steps, **okw):
+        o = oracle.Oracle(*shape, **okw)
+        t0 = time.perf_counter()
+        assert o.init(*fields) == 0
+        t_init = time.perf_counter() - t0
+        t0 = last = time.perf_counter()
+        for k in range(steps):
+            o.step(1)
+            if log and time.perf_counter() - last > 30.0:
+                last = time.perf_counter()
+                log(f"oracle {name}: {k + 1}/{steps} steps")
+        dt = time.perf_counter() - t0
+        n = int(np.prod(shape))
+        r = {"case": name, "cells": n, "steps": steps, "seconds": dt, "init_seconds": t_init,
+             "mlups": n * steps / dt / 1e6}
+        if log:
+            log(f"oracle {name}: {r['mlups']:.3f} MLUPS ({steps} steps, {dt:.1f} s)")
+        del o
+        return r
+
+    rows = []
+    # Sod tube 400 x 1 x 1, tau 0.5 with alpha(eps), all 400 steps
+    rows.append(timed("Sod 400x1x1", (400, 1, 1), inputs.sod_fields(400, temp_scale=0.5), 400, gamma=1.4, tau=0.5,
+                      kn_relax=True, faces=(eq, eq, 0, 0, 0, 0), newton_tol=1e-12))
+    # TGV at 32^3 and 128^3 (Ma 0.5, Re 1600)
+    for n, steps in ((32, 20),) if single_thread else ((32, 200), (128, 20)):
+        fields, kw = tgv_setup(n)
+        U = kw["mach"] * math.sqrt(kw["gamma"] * kw["T_ref"])
+        tau = oracle.tau_from_reynolds(U, kw["length_ref"], kw["reynolds"], kw["T_ref"])
+        rows.append(timed(f"TGV {n}^3", (n, n, n), fields, steps, gamma=kw["gamma"], tau=tau, kn_relax=True,
+                          newton_tol=1e-12))
+    # the obstacle flows from the free stream, a few steps (the sphere at half
+    # its size, 256 x 128 x 128: the cold start of the full grid alone takes
+    # minutes on the host)
+    cases = [] if single_thread else [("airfoil 2048x1024", precision_study.airfoil_case, 1.0, 5),
+                                      ("sphere 256x128x128", precision_study.sphere_case, 0.5, 3)]
+    for name, make, scale, steps in cases:
+        if log:
+            log(f"oracle {name}: cold start")
+        shape, solid, kw = make(scale)
+        n = int(np.prod(shape))
+        U = kw["mach"] * math.sqrt(kw["gamma"] * kw["T_ref"])
+        tau = oracle.tau_from_reynolds(U, kw["length_ref"], kw["reynolds"], kw["T_ref"])
+        u = np.zeros((3, n))
+        u[0] = U
+        rows.append(timed(name, shape, (np.ones(n), u, np.full(n, kw["T_ref"])), steps, gamma=kw["gamma"], tau=tau,
+                          kn_relax=True, faces=kw["faces"], solid=solid, newton_tol=1e-12))
+    return {"oracle_threads": threads, "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(), "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,11 +295,18 @@ def main():
     ap.add_argument("--serving-rate", type=float, default=3.0)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-only", action="store_true")
+    ap.add_argument("--cpu-table", action="store_true",
+                    help="time the FP64 oracle on the workloads' configurations instead (host only)")
+    ap.add_argument("--cpu-table-short", action="store_true", help="with --cpu-table: the short set (Sod, TGV 32^3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the single-domain path is not sharded across GPUs "
               "(see the multi-GPU design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.cpu_table:
+        res = cpu_table(args.cpu_table_short, log=lambda m: print("#", m, file=sys.stderr, flush=True))
+        print(json.dumps({"cpu_table": res}), flush=True)
+        return
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
