@@ -295,6 +295,8 @@ def main():
     ap.add_argument("--serving-rate", type=float, default=3.0)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-only", action="store_true")
+    ap.add_argument("--serving-sched", default="vft", choices=["vft", "srpt", "all"],
+                    help="round selection of the pool (with --serving-only)")
     ap.add_argument("--cpu-table", action="store_true",
                     help="time the FP64 oracle on the workloads' configurations instead (host only)")
     ap.add_argument("--cpu-table-short", action="store_true", help="with --cpu-table: the short set (Sod, TGV 32^3)")
@@ -316,7 +318,8 @@ def main():
     from paper_1910_13515_amd import lbm
     lbm.load()
     if args.serving_only:
-        print(json.dumps({"serving": serving_leg(args.serving_requests, args.serving_rate)}), flush=True)
+        print(json.dumps({"serving": serving_leg(args.serving_requests, args.serving_rate, sched=args.serving_sched)}),
+              flush=True)
         return
 
     main_res = run_mode(args.mode, args.n, args.steps, args.warmup)
