@@ -594,8 +594,10 @@ struct ParkHalf {
     }
     __device__ __forceinline__ void put(int i, float v) const
     {
+        // a 16-bit write of the low half; the high half stays zero
         const int k = (i < kQ ? 0 : 6) + shell(i < kQ ? i : i - kQ);
-        base[i * kBlockThreads] = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(v * inv_scale[k]));
+        *reinterpret_cast<uint16_t *>(base + i * kBlockThreads) =
+            __builtin_bit_cast(uint16_t, (_Float16)(v * inv_scale[k]));
     }
 };
 
@@ -870,8 +872,10 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f16(const SlotTa
                     typedef uint32_t v4u __attribute__((ext_vector_type(4)));
                     const v4u w0 = *reinterpret_cast<const v4u *>(lcol + i0 * kBlockThreads);
                     const v4u w1 = *reinterpret_cast<const v4u *>(lcol + i0 * kBlockThreads + 4);
-                    const v4u v = {(w0.x & 0xffffu) | (w0.y << 16), (w0.z & 0xffffu) | (w0.w << 16),
-                                   (w1.x & 0xffffu) | (w1.y << 16), (w1.z & 0xffffu) | (w1.w << 16)};
+                    // every word holds a half zero-extended (the gather's
+                    // 2-byte transfers and the collision's writes alike)
+                    const v4u v = {w0.x | (w0.y << 16), w0.z | (w0.w << 16), w1.x | (w1.y << 16),
+                                   w1.z | (w1.w << 16)};
                     __builtin_nontemporal_store(
                         v, reinterpret_cast<v4u __attribute__((address_space(1))) *>(dstb + (uint64_t)i0 * nS64 + voff));
                 }
