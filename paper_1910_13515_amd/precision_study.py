@@ -14,6 +14,7 @@ the relaxation factor alpha(eps) of one further step are reported per mode.
 
     python -m paper_1910_13515_amd.precision_study --case airfoil [--steps 20000] [--scale 1]
     python -m paper_1910_13515_amd.precision_study --case sphere  [--steps 2000]  [--scale 1] [--mach 1.5]
+    python -m paper_1910_13515_amd.precision_study --case tgv     [--steps 1000]  [--mach 0.5]
 
 ``--scale`` shrinks the domain and the body together (for quick checks).
 Prints one JSON object.
@@ -66,8 +67,21 @@ def sphere_case(scale: float = 1.0, mach: float = 1.5):
     return (nx, ny, nz), solid, kw
 
 
+def tgv_case(scale: float = 1.0, mach: float = 0.5):
+    """The benchmark's workload: periodic 128^3 compressible Taylor-Green
+    vortex at Ma 0.5, Re 1600, uniform T 0.5 (no obstacle; the mask is
+    empty).  The initial fields go in through ``fields``."""
+    n = int(round(128 * scale))
+    gamma, T0 = 1.4, 0.5
+    U = mach * np.sqrt(gamma * T0)
+    kw = dict(gamma=gamma, mach=mach, reynolds=1600.0, length_ref=n / (2 * np.pi), T_ref=T0, u_dir=(1.0, 0.0, 0.0),
+              kn_relax=True, fields=inputs.taylor_green_fields(n, U, T0))
+    return (n, n, n), np.zeros(n ** 3, dtype=np.uint8), kw
+
+
 CASES = {"airfoil": (airfoil_case, ("fp64", "fp32s"), 20000),
-         "sphere": (sphere_case, ("fp64", "fp32s", "fp16s", "fp16s@stream"), 2000)}
+         "sphere": (sphere_case, ("fp64", "fp32s", "fp16s", "fp16s@stream"), 2000),
+         "tgv": (tgv_case, ("fp64", "fp32s", "fp16s"), 1000)}
 
 
 def run(shape, solid, kw, storage, steps, chunk=1000, log=None):
@@ -77,7 +91,8 @@ def run(shape, solid, kw, storage, steps, chunk=1000, log=None):
     import torch
     mode = storage
     storage, _, ref = mode.partition("@")
-    s = lbm.Solver(shape, solid=solid, storage=storage, shift_ref=int(ref == "stream"), **kw)
+    s = lbm.Solver(shape, solid=solid if solid.any() else None, storage=storage, shift_ref=int(ref == "stream"),
+                   **kw)
     info = s.info()
     t0 = time.perf_counter()
     failed = 0
@@ -118,15 +133,16 @@ def errors(f, ref, fluid):
     return out
 
 
-def study(case: str, steps: int | None = None, scale: float = 1.0, modes=None, mach: float = 1.5, log=None):
+def study(case: str, steps: int | None = None, scale: float = 1.0, modes=None, mach: float | None = None, log=None):
     make, default_modes, default_steps = CASES[case]
     steps = default_steps if steps is None else steps
     modes = default_modes if modes is None else modes
-    shape, solid, kw = make(scale, mach)
+    shape, solid, kw = make(scale) if mach is None else make(scale, mach)
     fluid = solid.reshape(-1) == 0
     results = {"case": case, "shape": list(shape), "steps": steps, "scale": scale,
-               "solid_cells": int(solid.sum()), "params": {k: v for k, v in kw.items() if k != "faces"},
-               "faces": list(kw["faces"]), "modes": {}}
+               "solid_cells": int(solid.sum()),
+               "params": {k: v for k, v in kw.items() if k not in ("faces", "fields")},
+               "faces": list(kw.get("faces", (PER,) * 6)), "modes": {}}
     fields = {}
     for m in modes:
         f, summ = run(shape, solid, kw, m, steps, log=log)
@@ -150,7 +166,7 @@ def main():
     ap.add_argument("--modes", default=None,
                     help="comma-separated subset of fp64,fp32s,fp16s; fp32s@stream and fp16s@stream shift the "
                          "stored deviations by the free stream's equilibrium")
-    ap.add_argument("--mach", type=float, default=1.5)
+    ap.add_argument("--mach", type=float, default=None, help="default: the case's own (1.5; TGV 0.5)")
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available(), "the precision study needs a GPU"
