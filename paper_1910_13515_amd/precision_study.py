@@ -14,9 +14,11 @@ the relaxation factor alpha(eps) of one further step are reported per mode.
 
     python -m paper_1910_13515_amd.precision_study --case airfoil [--steps 20000] [--scale 1]
     python -m paper_1910_13515_amd.precision_study --case sphere  [--steps 2000]  [--scale 1] [--mach 1.5]
-    python -m paper_1910_13515_amd.precision_study --case tgv     [--steps 1000]  [--mach 0.5]
+    python -m paper_1910_13515_amd.precision_study --case tgv     [--steps 1000]  [--mach 0.5] [--plain-bgk]
 
 ``--scale`` shrinks the domain and the body together (for quick checks).
+``--plain-bgk`` turns the Knudsen-dependent relaxation off in every mode, so
+that its share in the reduced-precision error can be read off.
 Prints one JSON object.
 """
 from __future__ import annotations
@@ -133,11 +135,14 @@ def errors(f, ref, fluid):
     return out
 
 
-def study(case: str, steps: int | None = None, scale: float = 1.0, modes=None, mach: float | None = None, log=None):
+def study(case: str, steps: int | None = None, scale: float = 1.0, modes=None, mach: float | None = None, log=None,
+          plain_bgk: bool = False):
     make, default_modes, default_steps = CASES[case]
     steps = default_steps if steps is None else steps
     modes = default_modes if modes is None else modes
     shape, solid, kw = make(scale) if mach is None else make(scale, mach)
+    if plain_bgk:
+        kw = dict(kw, kn_relax=False)
     fluid = solid.reshape(-1) == 0
     results = {"case": case, "shape": list(shape), "steps": steps, "scale": scale,
                "solid_cells": int(solid.sum()),
@@ -167,13 +172,15 @@ def main():
                     help="comma-separated subset of fp64,fp32s,fp16s; fp32s@stream and fp16s@stream shift the "
                          "stored deviations by the free stream's equilibrium")
     ap.add_argument("--mach", type=float, default=None, help="default: the case's own (1.5; TGV 0.5)")
+    ap.add_argument("--plain-bgk", action="store_true",
+                    help="relax every cell with 1/tau (alpha(eps) off), in every mode including the FP64 reference")
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available(), "the precision study needs a GPU"
     torch.cuda.set_device(0)
     modes = args.modes.split(",") if args.modes else None
     res = study(args.case, args.steps, args.scale, modes, args.mach,
-                log=lambda m: print("#", m, file=sys.stderr, flush=True))
+                log=lambda m: print("#", m, file=sys.stderr, flush=True), plain_bgk=args.plain_bgk)
     print(json.dumps(res), flush=True)
 
 
