@@ -234,7 +234,8 @@ def cpu_table(single_thread=False, log=None):
     def timed(name, shape, fields, steps, **okw):
         o = oracle.Oracle(*shape, **okw)
         t0 = time.perf_counter()
-        assert o.init(*fields) == 0
+        if o.init(*fields) != 0:
+            raise RuntimeError("the oracle found no initial equilibrium")
         t_init = time.perf_counter() - t0
         t0 = last = time.perf_counter()
         for k in range(steps):
@@ -310,7 +311,8 @@ def main():
         print(json.dumps({"cpu_table": res}), flush=True)
         return
     import torch
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
     if args.copy_probe:
         copy_probe()

@@ -131,7 +131,9 @@ int64_t lbm_required_bytes(const lbm_params *params);
  * aligned, at least lbm_required_bytes()), uploads the obstacle and initial
  * fields and writes the initial state: every cell at the equilibrium of its
  * initial (rho, u, T), multipliers from a cold-started Newton solve.  Blocks
- * until the initial state is written.  On success *out owns the context. */
+ * until the initial state is written.  On success *out owns the context; on
+ * failure *out is NULL, no host memory is kept and lbm_last_error(NULL) holds
+ * the message. */
 int lbm_create(const lbm_params *params, void *dev_arena, int64_t arena_bytes, void *hip_stream, lbm_ctx **out);
 
 /* Advances nsteps >= 0 time steps (fused pull-stream and collide, Sec. 3).
@@ -259,7 +261,9 @@ int lbm_pool_wait(lbm_pool *pool, int32_t *finished, int32_t *nfinished);
 /* lbm_pool_launch followed by lbm_pool_wait. */
 int lbm_pool_run(lbm_pool *pool, int32_t *finished, int32_t *nfinished);
 
-/* Steps taken and steps still to run of a slot. */
+/* Steps taken and steps still to run of a slot.  The slot-level calls below
+ * return LBM_E_INVAL for a slot that is not admitted, with the message on the
+ * pool. */
 int lbm_pool_slot_progress(const lbm_pool *pool, int32_t slot, int64_t *steps_done, int64_t *steps_left);
 
 /* Moments of a slot, as lbm_moments().  LBM_E_INVAL for a slot of the round

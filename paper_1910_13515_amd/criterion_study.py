@@ -128,7 +128,8 @@ def main():
     ap.add_argument("--no-airfoil", action="store_true")
     args = ap.parse_args()
     import torch
-    assert torch.cuda.is_available(), "the criterion study needs a GPU"
+    if not torch.cuda.is_available():
+        raise SystemExit("the criterion study needs a GPU")
     torch.cuda.set_device(0)
     tols = [float(v) for v in args.tols.split(",")]
     modes = args.modes.split(",")

@@ -239,59 +239,12 @@ void build_links(const lbm_params &p, std::vector<uint64_t> &links)
             }
 }
 
-}  // namespace
-
-extern "C" {
-
-int32_t lbm_version(void) { return 10000; }
-
-int lbm_velocities(int32_t *out)
+// Everything lbm_create does once the context exists: defaults, derived
+// constants, obstacle links, the initial equilibrium, the slot table and the
+// persistent grid.  On failure c->err holds the message; the caller frees c.
+int create_in(lbm_ctx *c, const lbm_params *params)
 {
-    if (!out) return fail(nullptr, LBM_E_INVAL, "out is NULL");
-    for (int i = 0; i < kQ; ++i)
-        for (int a = 0; a < 3; ++a) out[3 * i + a] = vel(i, a);
-    return LBM_OK;
-}
-
-int64_t lbm_required_bytes(const lbm_params *params)
-{
-    const std::string v = validate(params);
-    if (!v.empty()) return fail(nullptr, LBM_E_INVAL, v);
-    return make_layout(*params).total;
-}
-
-int lbm_create(const lbm_params *params, void *dev_arena, int64_t arena_bytes, void *hip_stream, lbm_ctx **out)
-{
-    if (!out) return fail(nullptr, LBM_E_INVAL, "out is NULL");
-    *out = nullptr;
-    const std::string v = validate(params);
-    if (!v.empty()) return fail(nullptr, LBM_E_INVAL, v);
-    if (!dev_arena) return fail(nullptr, LBM_E_INVAL, "dev_arena is NULL");
-    if (reinterpret_cast<uintptr_t>(dev_arena) % kAlign != 0)
-        return fail(nullptr, LBM_E_INVAL, "dev_arena must be 256-byte aligned");
-    const Layout L = make_layout(*params);
-    if (arena_bytes < L.total)
-        return fail(nullptr, LBM_E_NOMEM,
-                    "arena of " + std::to_string(arena_bytes) + " bytes < required " + std::to_string(L.total));
-
-    {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
-            return fail(nullptr, LBM_E_DEVICE, "no HIP device");
-        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-            return fail(nullptr, LBM_E_DEVICE, std::string("library built for gfx950, device is ") + prop.gcnArchName);
-    }
-
-    lbm_ctx *c = new (std::nothrow) lbm_ctx();
-    if (!c) return fail(nullptr, LBM_E_NOMEM, "host allocation failed");
-    c->params = *params;
-    c->params.solid = nullptr;
-    c->params.init_rho = c->params.init_u = c->params.init_T = nullptr;
-    c->layout = L;
-    c->stream = static_cast<hipStream_t>(hip_stream);
-    c->arena = static_cast<char *>(dev_arena);
-    c->storage = params->storage;
+    const Layout &L = c->layout;
     lbm_params &p = c->params;
     if (p.rho_ref == 0.0) p.rho_ref = 1.0;
     if (p.T_ref == 0.0) p.T_ref = 0.5;
@@ -301,12 +254,6 @@ int lbm_create(const lbm_params *params, void *dev_arena, int64_t arena_bytes, v
     // to the FP32 residual floor near 1e-6) add a second update to most waves
     // without lowering the error against FP64, which storage rounding sets.
     if (p.newton_tol == 0.0) p.newton_tol = p.storage == LBM_STORE_FP64 ? 1e-12 : 1e-5;
-
-    auto bail = [&](int code) {
-        g_last_error = c->err;
-        delete c;
-        return code;
-    };
 
     const double Cv = 1.0 / (p.gamma - 1.0);
     const double delta = 2.0 * Cv - 3.0;
@@ -320,9 +267,9 @@ int lbm_create(const lbm_params *params, void *dev_arena, int64_t arena_bytes, v
     double rest[kQ + kM], stream_eq[kQ + kM];
     const double zero[3] = {0.0, 0.0, 0.0};
     int rc = device_equilibrium(c, 1.0, zero, p.T_ref, rest);
-    if (rc != LBM_OK) return bail(rc);
+    if (rc != LBM_OK) return rc;
     rc = device_equilibrium(c, p.rho_ref, c->u_ref, p.T_ref, stream_eq);
-    if (rc != LBM_OK) return bail(rc);
+    if (rc != LBM_OK) return rc;
     c->shear_response = shear_response(rest, p.T_ref);
 
     if (p.tau > 0.0) {
@@ -477,7 +424,7 @@ int lbm_create(const lbm_params *params, void *dev_arena, int64_t arena_bytes, v
             if (!(host[i] > 0.0) || !(host[4 * n + i] > 0.0) || !std::isfinite(host[i] + host[n + i] + host[2 * n + i] +
                                                                                  host[3 * n + i] + host[4 * n + i])) {
                 c->err = "initial fields need finite values with rho > 0 and T > 0";
-                return bail(LBM_E_INVAL);
+                return LBM_E_INVAL;
             }
         double *d_fields = at<double>(c->arena, L.fields);
         unsigned long long *d_failed = at<unsigned long long>(c->arena, L.failed);
@@ -492,7 +439,7 @@ int lbm_create(const lbm_params *params, void *dev_arena, int64_t arena_bytes, v
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         if (failed) {
             c->err = std::to_string(failed) + " initial cells have no 13-moment equilibrium";
-            return bail(LBM_E_NONREALIZABLE);
+            return LBM_E_NONREALIZABLE;
         }
     }
 
@@ -520,6 +467,68 @@ int lbm_create(const lbm_params *params, void *dev_arena, int64_t arena_bytes, v
         grid = std::min(grid, kMaxGrid);
         grid = std::max(8, grid / 8 * 8);
         c->grid = grid;
+    }
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t lbm_version(void) { return 10000; }
+
+int lbm_velocities(int32_t *out)
+{
+    if (!out) return fail(nullptr, LBM_E_INVAL, "out is NULL");
+    for (int i = 0; i < kQ; ++i)
+        for (int a = 0; a < 3; ++a) out[3 * i + a] = vel(i, a);
+    return LBM_OK;
+}
+
+int64_t lbm_required_bytes(const lbm_params *params)
+{
+    const std::string v = validate(params);
+    if (!v.empty()) return fail(nullptr, LBM_E_INVAL, v);
+    return make_layout(*params).total;
+}
+
+int lbm_create(const lbm_params *params, void *dev_arena, int64_t arena_bytes, void *hip_stream, lbm_ctx **out)
+{
+    if (!out) return fail(nullptr, LBM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    const std::string v = validate(params);
+    if (!v.empty()) return fail(nullptr, LBM_E_INVAL, v);
+    if (!dev_arena) return fail(nullptr, LBM_E_INVAL, "dev_arena is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_arena) % kAlign != 0)
+        return fail(nullptr, LBM_E_INVAL, "dev_arena must be 256-byte aligned");
+    const Layout L = make_layout(*params);
+    if (arena_bytes < L.total)
+        return fail(nullptr, LBM_E_NOMEM,
+                    "arena of " + std::to_string(arena_bytes) + " bytes < required " + std::to_string(L.total));
+
+    {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+            return fail(nullptr, LBM_E_DEVICE, "no HIP device");
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            return fail(nullptr, LBM_E_DEVICE, std::string("library built for gfx950, device is ") + prop.gcnArchName);
+    }
+
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(nullptr, LBM_E_NOMEM, "host allocation failed");
+    c->params = *params;
+    c->params.solid = nullptr;
+    c->params.init_rho = c->params.init_u = c->params.init_T = nullptr;
+    c->layout = L;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->arena = static_cast<char *>(dev_arena);
+    c->storage = params->storage;
+    const int rc = create_in(c, params);
+    if (rc != LBM_OK) {
+        g_last_error = c->err;
+        delete c;
+        return rc;
     }
     *out = c;
     return LBM_OK;
@@ -756,7 +765,7 @@ struct lbm_pool {
     int64_t seq = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    std::string err = "no error";
+    mutable std::string err = "no error";  // also set by the const queries
 };
 
 namespace {
@@ -792,6 +801,14 @@ void pool_free(lbm_pool *p)
 }
 
 bool slot_ok(const lbm_pool *p, int32_t slot) { return p && slot >= 0 && slot < p->max_slots && p->slots[slot].used; }
+
+// Error of a slot-level call: the pool's message when there is a pool.
+int slot_fail(const lbm_pool *p)
+{
+    if (!p) return fail(nullptr, LBM_E_INVAL, "pool is NULL");
+    p->err = "invalid slot";
+    return LBM_E_INVAL;
+}
 
 double host_seconds()
 {
@@ -954,7 +971,12 @@ int lbm_pool_admit(lbm_pool *p, const lbm_params *params, int32_t nsteps, int32_
         p->heap.release(off, need);
         return pool_fail(p, rc, lbm_last_error(nullptr));
     }
-    POOL_TRY(p, hipEventRecord(p->admitted, p->admit_stream));
+    const hipError_t e = hipEventRecord(p->admitted, p->admit_stream);
+    if (e != hipSuccess) {
+        (void)lbm_destroy(ctx);
+        p->heap.release(off, need);
+        return pool_fail(p, LBM_E_DEVICE, std::string("admission event: ") + hipGetErrorString(e));
+    }
     PoolSlot &s = p->slots[slot];
     s.used = true;
     s.in_round = false;
@@ -1046,7 +1068,7 @@ int lbm_pool_run(lbm_pool *p, int32_t *finished, int32_t *nfinished)
 
 int lbm_pool_slot_progress(const lbm_pool *p, int32_t slot, int64_t *steps_done, int64_t *steps_left)
 {
-    if (!slot_ok(p, slot)) return fail(nullptr, LBM_E_INVAL, "invalid pool or slot");
+    if (!slot_ok(p, slot)) return slot_fail(p);
     if (steps_done) *steps_done = p->slots[slot].steps_total - p->slots[slot].steps_left;
     if (steps_left) *steps_left = p->slots[slot].steps_left;
     return LBM_OK;
@@ -1054,7 +1076,7 @@ int lbm_pool_slot_progress(const lbm_pool *p, int32_t slot, int64_t *steps_done,
 
 int lbm_pool_moments(lbm_pool *p, int32_t slot, double *out_host, double *totals)
 {
-    if (!slot_ok(p, slot)) return fail(nullptr, LBM_E_INVAL, "invalid pool or slot");
+    if (!slot_ok(p, slot)) return slot_fail(p);
     if (p->slots[slot].in_round) return pool_fail(p, LBM_E_INVAL, "slot is part of the round in flight");
     const int rc = lbm_moments(p->slots[slot].ctx, out_host, totals);
     if (rc != LBM_OK) p->err = lbm_last_error(p->slots[slot].ctx);
@@ -1063,7 +1085,7 @@ int lbm_pool_moments(lbm_pool *p, int32_t slot, double *out_host, double *totals
 
 int lbm_pool_release(lbm_pool *p, int32_t slot)
 {
-    if (!slot_ok(p, slot)) return fail(nullptr, LBM_E_INVAL, "invalid pool or slot");
+    if (!slot_ok(p, slot)) return slot_fail(p);
     if (p->slots[slot].in_round) return pool_fail(p, LBM_E_INVAL, "slot is part of the round in flight");
     PoolSlot &s = p->slots[slot];
     const int rc = lbm_destroy(s.ctx);

@@ -105,7 +105,8 @@ def main():
     ap.add_argument("--png", default=None)
     args = ap.parse_args()
     import torch
-    assert torch.cuda.is_available(), "the map needs a GPU"
+    if not torch.cuda.is_available():
+        raise SystemExit("the map needs a GPU")
     torch.cuda.set_device(0)
     shape, solid, eps, iters = run(args.steps, args.scale, args.storage,
                                    log=lambda m: print("#", m, file=sys.stderr, flush=True))

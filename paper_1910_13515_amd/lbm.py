@@ -227,10 +227,13 @@ def lbm_get_state(ctx, n: int):
     return f, g, lam
 
 
-def lbm_set_state(ctx, f, g, lam):
-    f = np.ascontiguousarray(f, dtype=np.float64)
-    g = np.ascontiguousarray(g, dtype=np.float64)
-    lam = np.ascontiguousarray(lam, dtype=np.float64)
+def lbm_set_state(ctx, f, g, lam, n: int):
+    """f, g: 39*n doubles each, lam: 13*n (the library reads exactly that many)."""
+    f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+    g = np.ascontiguousarray(g, dtype=np.float64).reshape(-1)
+    lam = np.ascontiguousarray(lam, dtype=np.float64).reshape(-1)
+    if f.size != 39 * n or g.size != 39 * n or lam.size != 13 * n:
+        raise ValueError(f"state of {n} cells needs 39n, 39n and 13n values; got {f.size}, {g.size}, {lam.size}")
     _check(load().lbm_set_state(ctx, _ptr(f), _ptr(g), _ptr(lam)), ctx)
 
 
@@ -283,12 +286,14 @@ class Solver:
         self._keep = []
         if solid is not None:
             s = np.ascontiguousarray(solid, dtype=np.uint8).reshape(-1)
-            assert s.size == self.n
+            if s.size != self.n:
+                raise ValueError(f"solid mask has {s.size} cells, the grid {self.n}")
             self._keep.append(s)
             self.params.solid = s.ctypes.data
         if fields is not None:
             rho, u, T = (np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in fields)
-            assert rho.size == self.n and u.size == 3 * self.n and T.size == self.n
+            if rho.size != self.n or u.size != 3 * self.n or T.size != self.n:
+                raise ValueError(f"fields of {self.n} cells need n, 3n and n values; got {rho.size}, {u.size}, {T.size}")
             self._keep += [rho, u, T]
             self.params.init_rho = rho.ctypes.data
             self.params.init_u = u.ctypes.data
@@ -335,7 +340,7 @@ class Solver:
         return lbm_diagnostics(self.ctx, self.n)
 
     def set_state(self, f, g, lam):
-        lbm_set_state(self.ctx, f, g, lam)
+        lbm_set_state(self.ctx, f, g, lam, self.n)
 
     def info(self) -> lbm_info:
         return lbm_get_info(self.ctx)

@@ -176,7 +176,8 @@ def main():
                     help="relax every cell with 1/tau (alpha(eps) off), in every mode including the FP64 reference")
     args = ap.parse_args()
     import torch
-    assert torch.cuda.is_available(), "the precision study needs a GPU"
+    if not torch.cuda.is_available():
+        raise SystemExit("the precision study needs a GPU")
     torch.cuda.set_device(0)
     modes = args.modes.split(",") if args.modes else None
     res = study(args.case, args.steps, args.scale, modes, args.mach,

@@ -80,7 +80,8 @@ def main():
     args = ap.parse_args()
     grid = GRID if not args.grid else [tuple(float(v) for v in g.split(":")) for g in args.grid.split(",")]
     import torch
-    assert torch.cuda.is_available(), "the stability map needs a GPU"
+    if not torch.cuda.is_available():
+        raise SystemExit("the stability map needs a GPU")
     torch.cuda.set_device(0)
     res = sweep(args.steps, args.scale, args.storage, grid, log=lambda m: print("#", m, file=sys.stderr, flush=True))
     print(json.dumps({"case": "airfoil", "scale": args.scale, "steps": args.steps, "storage": args.storage,

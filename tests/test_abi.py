@@ -61,6 +61,15 @@ def test_parameter_validation_without_device(L):
     assert b"NULL" in lbm.load().lbm_last_error(None)
 
 
+def test_state_arrays_of_the_wrong_size_are_refused_before_the_call(L):
+    import numpy as np
+    n = 5
+    with pytest.raises(ValueError):
+        lbm.lbm_set_state(None, np.zeros(39 * n), np.zeros(39 * n), np.zeros(13 * n - 1), n)
+    with pytest.raises(ValueError):
+        lbm.lbm_set_state(None, np.zeros(39 * n + 1), np.zeros(39 * n), np.zeros(13 * n), n)
+
+
 def test_required_bytes_scale_with_storage(L):
     n = 64 * 32 * 16
     b64 = lbm.lbm_required_bytes(lbm.make_params((64, 32, 16), tau=0.6, storage="fp64"))

@@ -288,6 +288,8 @@ def test_nonrealizable_initial_state_is_rejected(lbm):
     with pytest.raises(lbm.LbmError) as e:
         lbm.Solver(shape, fields=(rho, u, T), storage="fp64", tau=0.6)
     assert e.value.code == lbm.LBM_E_NONREALIZABLE
+    # the failed create keeps nothing and leaves its message for ctx = NULL
+    assert "initial cells have no 13-moment equilibrium" in str(e.value)
 
 
 def test_arena_too_small_is_rejected(lbm):

@@ -70,6 +70,10 @@ def test_admission_by_footprint_and_release():
         pool.release(b)
     with pytest.raises(lbm.LbmError):
         pool.launch()
+    # a slot that was never admitted: an argument error, reported on the pool
+    with pytest.raises(lbm.LbmError) as e:
+        pool.release(7)
+    assert e.value.code == lbm.LBM_E_INVAL and "invalid slot" in str(e.value)
     done = pool.wait()
     for _ in range(2):
         done += pool.run()
