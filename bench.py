@@ -82,7 +82,8 @@ def run_mode(mode, n, steps, warmup):
         "alpha_hist": list(st.alpha_hist),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_cell": BYTES_PER_CELL[mode], "cells_per_launch": cells},
+                     "bytes_per_cell": BYTES_PER_CELL[mode], "cells_per_launch": cells,
+                     "floor_ms": bytes_launch / (HBM_PEAK_GBS * 1e9) * 1e3},
     }
 
 
@@ -133,7 +134,16 @@ def measured_alu(mode: str, ms_per_step: float):
     peak = 256 * 4 * 2.4e9 / 4.0
     achieved = m["valu_instr_per_launch"] / (ms_per_step * 1e-3)
     return {"valu_instr_per_cell": m["valu_instr_per_cell"], "achieved_ginstr_s": achieved / 1e9,
-            "peak_ginstr_s": peak / 1e9, "frac": achieved / peak}
+            "peak_ginstr_s": peak / 1e9, "frac": achieved / peak,
+            "floor_ms": m["valu_instr_per_launch"] / peak * 1e3}
+
+
+def with_ceiling(roof, alu):
+    """Names the higher of the two floors (HBM bytes at peak bandwidth, VALU
+    instructions at peak issue): the ceiling that binds the launch."""
+    if alu is not None:
+        alu["binding_ceiling"] = "alu" if alu["floor_ms"] > roof["floor_ms"] else "hbm"
+    return alu
 
 
 def copy_probe(gib=1, reps=5):
@@ -341,7 +351,7 @@ def main():
     roof["traffic"] = measured_traffic(args.mode)
     for m, r in modes.items():
         r["roofline"]["traffic"] = measured_traffic(m)
-        r["alu"] = measured_alu(m, r["ms_per_step"])
+        r["alu"] = with_ceiling(r["roofline"], measured_alu(m, r["ms_per_step"]))
     out = {
         "metric": "GLUPS (D3Q39 f+g cell updates per second)",
         "value": main_res["glups"],
@@ -360,7 +370,7 @@ def main():
                    "tau": main_res["tau"], "newton_iterations_per_cell": main_res["newton_iterations_per_cell"],
                    "alpha_hist": main_res["alpha_hist"]},
         "roofline": roof,
-        "alu": measured_alu(args.mode, main_res["ms_per_step"]),
+        "alu": with_ceiling(roof, measured_alu(args.mode, main_res["ms_per_step"])),
         "cpu_baseline": cpu,
         "modes": modes,
         "serving": serving,
