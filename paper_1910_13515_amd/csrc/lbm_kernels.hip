@@ -1,11 +1,13 @@
 // HIP kernels of the D3Q39 13-moment DDF lattice Boltzmann step for gfx950.
 //
-// The hot kernel, step_kernel, is the fused pull-stream-and-collide step of
-// Sec. 3 of the paper for f and g: each lane gathers the 78 populations of
-// one cell from shells up to three cells away, takes the moments, solves the
-// 13 Lagrange multipliers by warm-started Newton (Sec. 5 table), evaluates
-// the Knudsen sensor (Eq. eq:DeltaAvg) and alpha (Eq. eq:alpha), and writes
-// the BGK-relaxed populations to the other ping-pong buffer.
+// The hot kernels, step_kernel_f64, step_kernel_f32 and step_kernel_f16 (one
+// per storage mode), are the fused pull-stream-and-collide step of Sec. 3 of
+// the paper for f and g: each lane gathers the 78 populations of one cell
+// from shells up to three cells away, takes the moments, solves the 13
+// Lagrange multipliers by warm-started Newton (Sec. 5 table), evaluates the
+// Knudsen sensor (Eq. eq:DeltaAvg) and alpha (Eq. eq:alpha), and writes the
+// BGK-relaxed populations to the other ping-pong buffer.  diag_kernel
+// evaluates the same step up to the sensor, with a gather into registers.
 //
 // Memory layout (structure of arrays, x fastest): a population buffer is
 // [f_0..f_38, g_0..g_38][n]; the multipliers are [13][n].  A wave owns 64
@@ -19,18 +21,6 @@
 
 #include "equilibrium.h"
 #include "slot.h"
-
-// FP32-shifted storage: 1 = step_kernel_f32 (gather into LDS by direct
-// loads, 16-byte row stores); 0 = step_kernel<float>
-#ifndef LBM_FP32_DMA
-#define LBM_FP32_DMA 1
-#endif
-#ifndef LBM_FP64_DMA
-#define LBM_FP64_DMA 1
-#endif
-#ifndef LBM_FP16_DMA
-#define LBM_FP16_DMA 1
-#endif
 
 namespace lbm13 {
 
@@ -211,39 +201,6 @@ __device__ __forceinline__ void gather_pairs(const SlotDesc &d, gcbyte *srcb, ui
     (gather_pair<P, S, C>(d, srcb, nS64, nS, cellS, links, Xo, Yo, Zo, pk, acc), ...);
 }
 
-// BGK update of velocity I for f and g; stores the result
-template <int I, class S, class C>
-__device__ __forceinline__ void relax_one(const SlotDesc &d, gbyte *dstb, uint64_t nS64, uint32_t cellS, C rho, C dT,
-                                          C omega, C f0, const C *fp, const C *fm, const Park<C> &pk)
-{
-    const C feq = rho * feq_of<I>(f0, fp, fm);
-    const C geq = dT * feq;
-    const C hf = pk.get(I), hg = pk.get(kQ + I);
-    C of, og;
-    if constexpr (StoreTraits<S>::kShift) {
-        // deviations from the shift weights: D* = D + omega ((h_eq - w) - D)
-        of = hf + omega * ((feq - C(d.shift_w[I])) - hf);
-        og = hg + omega * ((geq - C(d.shift_w[kQ + I])) - hg);
-        if constexpr (StoreTraits<S>::kScale) {
-            of *= C(d.shell_inv_scale[0][shell(I)]);
-            og *= C(d.shell_inv_scale[1][shell(I)]);
-        }
-    } else {
-        of = hf + omega * (feq - hf);
-        og = hg + omega * (geq - hg);
-    }
-    gstore<S>(dstb + (uint64_t)I * nS64, cellS, static_cast<S>(of));
-    gstore<S>(dstb + (uint64_t)(kQ + I) * nS64, cellS, static_cast<S>(og));
-}
-
-template <class S, class C, int... I>
-__device__ __forceinline__ void relax_all(const SlotDesc &d, gbyte *dstb, uint64_t nS64, uint32_t cellS, C rho, C dT,
-                                          C omega, C f0, const C *fp, const C *fm, const Park<C> &pk,
-                                          std::integer_sequence<int, I...>)
-{
-    (relax_one<I, S, C>(d, dstb, nS64, cellS, rho, dT, omega, f0, fp, fm, pk), ...);
-}
-
 template <int I, class S, class C, class PK>
 __device__ __forceinline__ C eps_term(const SlotDesc &d, C rho, C f0, const C *fp, const C *fm, const PK &pk)
 {
@@ -266,22 +223,19 @@ __device__ __forceinline__ C eps_sum(const SlotDesc &d, C rho, C f0, const C *fp
 
 using VelSeq = std::make_integer_sequence<int, kQ>;
 
-// One fluid cell: gather, moments, Newton, sensor, BGK, store.  (y, z) are
-// uniform across the wave; x is the lane's coordinate.  kDiag: stop after the
-// sensor and write eps (NaN where the solve fails) to diag[cell] and the
-// Newton iterations to diag[n + cell]; nothing else is written.
-template <class S, bool kDiag = false>
-__device__ __forceinline__ void update_cell(const SlotDesc &d, const S *src, S *dst, int x, int y, int z,
-                                            uint32_t cell, const Park<typename StoreTraits<S>::C> &pk,
-                                            int32_t (&acc)[kStatWords], double *diag = nullptr)
+// One fluid cell of the next step up to the sensor: gather, moments, Newton,
+// sensor.  Writes eps (NaN where the solve fails) to diag[cell] and the Newton
+// iterations to diag[n + cell]; the state is left unchanged.  (y, z) are
+// uniform across the wave; x is the lane's coordinate.
+template <class S>
+__device__ __forceinline__ void diag_cell(const SlotDesc &d, const S *src, int x, int y, int z, uint32_t cell,
+                                          const Park<typename StoreTraits<S>::C> &pk, double *diag)
 {
     using C = typename StoreTraits<S>::C;
     const uint64_t links = d.has_links ? d.links[cell] : 0ull;
     if (links >> 63) {  // solid
-        if constexpr (kDiag) {
-            diag[cell] = __builtin_nan("");
-            diag[d.n + cell] = -1.0;
-        }
+        diag[cell] = __builtin_nan("");
+        diag[d.n + cell] = -1.0;
         return;
     }
 
@@ -362,36 +316,10 @@ __device__ __forceinline__ void update_cell(const SlotDesc &d, const S *src, S *
         project_invariants(f0, fp, fm, resid, d.proj_w, d.proj_inv, d.proj_inv_w2, PairSeq{});
     }
 
-    // Knudsen sensor over f (Eq. eq:DeltaAvg) and relaxation branch (Eq. eq:alpha)
+    // Knudsen sensor over f (Eq. eq:DeltaAvg)
     const C eps = eps_sum<S, C>(d, rho, f0, fp, fm, pk, VelSeq{}) * C(1.0 / kQ);
-    int br = 0;
-    if (d.kn_relax) br = (eps < C(1e-2)) ? 0 : (eps < C(1e-1)) ? 1 : (eps < C(1)) ? 2 : 3;
-    // a cell whose multipliers were not found is not collided (omega = 0
-    // against the finite values the solver leaves): gathered values stored
-    // unchanged, multipliers kept for the next warm start
-    const bool failed = status == kFailed;
-    if constexpr (kDiag) {
-        diag[cell] = failed ? __builtin_nan("") : (double)eps;
-        diag[d.n + cell] = (double)iters;
-        return;
-    }
-    const C omega = failed ? C(0) : C(br == 0 ? d.omega[0] : br == 1 ? d.omega[1] : br == 2 ? d.omega[2] : d.omega[3]);
-    const C dT = C(d.delta) * T;
-
-    relax_all<S, C>(d, (gbyte *)dst, nS64, cellS, rho, dT, omega, f0, fp, fm, pk, VelSeq{});
-    if (!failed) {
-#pragma unroll
-        for (int k = 0; k < kM; ++k) gstore<C>(lamb + (uint64_t)k * nC64, cellC, lam[k]);
-    }
-
-    acc[0] += iters;
-    acc[1] = iters > acc[1] ? iters : acc[1];
-    acc[2] += failed;
-    acc[3] += status == kConvergedCold;
-    acc[4] += !failed && br == 0;
-    acc[5] += !failed && br == 1;
-    acc[6] += !failed && br == 2;
-    acc[7] += !failed && br == 3;
+    diag[cell] = status == kFailed ? __builtin_nan("") : (double)eps;
+    diag[d.n + cell] = (double)iters;
 }
 
 // Locate the slot that owns logical block b (uniform across the block).
@@ -400,66 +328,6 @@ __device__ __forceinline__ int find_slot(const SlotTable *tab, int b)
     int s = 0;
     while (s + 1 < tab->nslots && tab->block_start[s + 1] <= b) ++s;
     return s;
-}
-
-// Batched fused step.  Launch j of a sequence advances every slot with
-// j < steps_todo from buffer (parity0 + j) & 1 to the other one.  The grid
-// (a multiple of 8 blocks) is persistent: blocks stride over the logical
-// blocks of all slots, each XCD over its own contiguous range.
-template <class S>
-__global__ __launch_bounds__(kBlockThreads, StoreTraits<S>::kWavesPerSimd) void step_kernel(const SlotTable *__restrict__ tab, int j,
-                                                             int64_t *__restrict__ stats)
-{
-    using C = typename StoreTraits<S>::C;
-    __shared__ C park[2 * kQ * kBlockThreads];
-    const Park<C> pk{park + threadIdx.x};
-    int32_t acc[kStatWords] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    const int total = tab->total_blocks;
-    const int xcd = blockIdx.x & 7;
-    const int per_xcd = gridDim.x >> 3;
-    const int lo = (int)(((int64_t)total * xcd) >> 3);
-    const int hi = (int)(((int64_t)total * (xcd + 1)) >> 3);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    for (int b = lo + (int)(blockIdx.x >> 3); b < hi; b += per_xcd) {
-        const int s = find_slot(tab, b);
-        const SlotDesc &d = tab->slot[s];
-        if (j >= d.steps_todo) continue;
-        const int64_t seg = (int64_t)(b - tab->block_start[s]) * kWavesPerBlock + wave;
-        if (seg >= d.segments) continue;
-        const int segx = (int)(seg % d.nsegx);
-        const int row = (int)(seg / d.nsegx);
-        const int y = row % d.ny;
-        const int z = row / d.ny;
-        const int x = segx * kSegment + lane;
-        int32_t it_cell = 0;
-        if (x < d.nx && is_fluid_coord(d, x, y, z)) {
-            const int par = (d.parity0 + j) & 1;
-            const S *src = static_cast<const S *>(d.buf[par]);
-            S *dst = static_cast<S *>(d.buf[par ^ 1]);
-            const uint32_t cell = (uint32_t)x + (uint32_t)d.nx * ((uint32_t)y + (uint32_t)d.ny * (uint32_t)z);
-            const int32_t it_before = acc[0];
-            update_cell<S>(d, src, dst, x, y, z, cell, pk, acc);
-            it_cell = acc[0] - it_before;
-        }
-        // per-wave cost: the wave runs as many updates as its slowest cell
-        // (all 64 lanes are converged here)
-        if (stats) {
-            const int32_t wmax = wave_max(it_cell);
-            acc[8] += lane == 0 ? wmax : 0;
-            acc[9] += lane == 0 ? 1 : 0;
-        }
-    }
-    if (stats) {
-        int64_t red[kStatWords];
-#pragma unroll
-        for (int k = 0; k < kStatWords; ++k) red[k] = (k == 1) ? wave_max(acc[k]) : wave_sum(acc[k]);
-        if (lane == 0) {
-            int64_t *p = stats + ((int64_t)blockIdx.x * kWavesPerBlock + wave) * kStatWords;
-#pragma unroll
-            for (int k = 0; k < kStatWords; ++k) p[k] = (k == 1) ? (red[k] > p[k] ? red[k] : p[k]) : p[k] + red[k];
-        }
-    }
 }
 
 // Diagnostics of the next step of one solve (slot 0 of tab, launch index j):
@@ -473,7 +341,6 @@ __global__ __launch_bounds__(kBlockThreads, StoreTraits<S>::kWavesPerSimd) void 
     using C = typename StoreTraits<S>::C;
     __shared__ C park[2 * kQ * kBlockThreads];
     const Park<C> pk{park + threadIdx.x};
-    int32_t acc[kStatWords] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const SlotDesc &d = tab->slot[0];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -490,7 +357,7 @@ __global__ __launch_bounds__(kBlockThreads, StoreTraits<S>::kWavesPerSimd) void 
         if (is_fluid_coord(d, x, y, z)) {
             const int par = (d.parity0 + j) & 1;
             const S *src = static_cast<const S *>(d.buf[par]);
-            update_cell<S, true>(d, src, nullptr, x, y, z, cell, pk, acc, diag);
+            diag_cell<S>(d, src, x, y, z, cell, pk, diag);
         } else {
             diag[cell] = __builtin_nan("");
             diag[d.n + cell] = -1.0;
@@ -1407,13 +1274,6 @@ __global__ void copy_lam_kernel(SlotDesc d, int k, int to_device, double *__rest
 
 namespace lbm13 {
 
-template <class S>
-static hipError_t launch_step_t(const SlotTable *tab, int grid, int j, int64_t *stats, hipStream_t st)
-{
-    hipLaunchKernelGGL(step_kernel<S>, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
-    return hipGetLastError();
-}
-
 hipError_t launch_diag(int storage, const SlotTable *tab, int grid, int j, double *diag, hipStream_t st)
 {
     switch (storage) {
@@ -1428,53 +1288,30 @@ hipError_t launch_step(int storage, const SlotTable *tab, int grid, int j, int64
 {
     switch (storage) {
     case kStoreF64:
-#if LBM_FP64_DMA
         if (stats)
             hipLaunchKernelGGL(step_kernel_f64<true>, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
         else
             hipLaunchKernelGGL(step_kernel_f64<false>, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
-        return hipGetLastError();
-#else
-        return launch_step_t<double>(tab, grid, j, stats, st);
-#endif
+        break;
     case kStoreF32:
-#if LBM_FP32_DMA
         hipLaunchKernelGGL(step_kernel_f32, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
-        return hipGetLastError();
-#else
-        return launch_step_t<float>(tab, grid, j, stats, st);
-#endif
+        break;
     default:
-#if LBM_FP16_DMA
         if (stats)
             hipLaunchKernelGGL(step_kernel_f16<true>, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
         else
             hipLaunchKernelGGL(step_kernel_f16<false>, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
-        return hipGetLastError();
-#else
-        return launch_step_t<_Float16>(tab, grid, j, stats, st);
-#endif
+        break;
     }
+    return hipGetLastError();
 }
 
 const void *step_kernel_symbol(int storage)
 {
     switch (storage) {
-#if LBM_FP64_DMA
     case kStoreF64: return reinterpret_cast<const void *>(&step_kernel_f64<false>);
-#else
-    case kStoreF64: return reinterpret_cast<const void *>(&step_kernel<double>);
-#endif
-#if LBM_FP32_DMA
     case kStoreF32: return reinterpret_cast<const void *>(&step_kernel_f32);
-#else
-    case kStoreF32: return reinterpret_cast<const void *>(&step_kernel<float>);
-#endif
-#if LBM_FP16_DMA
     default: return reinterpret_cast<const void *>(&step_kernel_f16<false>);
-#else
-    default: return reinterpret_cast<const void *>(&step_kernel<_Float16>);
-#endif
     }
 }
 

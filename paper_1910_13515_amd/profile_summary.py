@@ -30,9 +30,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PROFILES = os.path.join(ROOT, "profiles")
 
 # kernel-name fragment -> storage mode
-STEP_KERNELS = {"fp64": ("step_kernel_f64", "step_kernel<double>", "step_kernelIdE"),
-                "fp32s": ("step_kernel_f32",),
-                "fp16s": ("step_kernel_f16", "step_kernel<_Float16>", "step_kernelIDF16_")}
+STEP_KERNELS = {"fp64": ("step_kernel_f64",), "fp32s": ("step_kernel_f32",), "fp16s": ("step_kernel_f16",)}
 BYTES_PER_CELL = {"fp64": 2 * 78 * 8 + 2 * 13 * 8, "fp32s": 2 * 78 * 4 + 2 * 13 * 4, "fp16s": 2 * 78 * 2 + 2 * 13 * 4}
 CELLS = 128 ** 3
 COPY_BYTES = 1 << 30
