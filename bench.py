@@ -66,6 +66,7 @@ def run_mode(mode, n, steps, warmup):
     ms = start.elapsed_time(end)
     st = s.step(1, stats=True)  # statistics of one further step (not timed)
     info = s.info()
+    fields, _ = s.moments()  # (rho, u, T) after warmup + steps + 1, for the error against FP64
     s.close()
     del s
     torch.cuda.empty_cache()
@@ -74,6 +75,8 @@ def run_mode(mode, n, steps, warmup):
     bytes_launch = BYTES_PER_CELL[mode] * cells
     achieved = bytes_launch / (ms_step * 1e-3) / 1e9
     return {
+        "fields": fields,
+        "steps_total": warmup + steps + 1,
         "glups": glups,
         "ms_per_step": ms_step,
         "tau": info.tau,
@@ -349,11 +352,23 @@ def main():
     cpu = None if args.no_cpu else cpu_baseline()
     roof = dict(main_res["roofline"])
     roof["traffic"] = measured_traffic(args.mode)
+    ref = main_res.pop("fields")
+    main_res.pop("steps_total")
     for m, r in modes.items():
         r["roofline"]["traffic"] = measured_traffic(m)
         r["alu"] = with_ceiling(r["roofline"], measured_alu(m, r["ms_per_step"]))
+        f = r.pop("fields")
+        if args.mode == "fp64":
+            # same initial state and step count as the FP64 run: relative L2
+            # errors of (rho, u, T) over all cells
+            import numpy as np
+
+            from paper_1910_13515_amd import precision_study
+            e = precision_study.errors(f, ref, np.ones(f.shape[1], dtype=bool))
+            r["vs_fp64"] = {"after_steps": r["steps_total"], **{k: v for k, v in e.items() if k.startswith("l2_")}}
+        r.pop("steps_total")
     out = {
-        "metric": "GLUPS (D3Q39 f+g cell updates per second)",
+        "metric": "GLUPS (D3Q39 f+g) & % HBM roofline, FP32/FP16 vs FP64 at stated error; p99",
         "value": main_res["glups"],
         "unit": "GLUPS",
         "n_gpus": 1,

@@ -18,7 +18,9 @@ the relaxation factor alpha(eps) of one further step are reported per mode.
 
 ``--scale`` shrinks the domain and the body together (for quick checks).
 ``--plain-bgk`` turns the Knudsen-dependent relaxation off in every mode, so
-that its share in the reduced-precision error can be read off.
+that its share in the reduced-precision error can be read off.  ``--every N``
+runs the modes side by side instead and reports their errors against FP64
+every N steps (the error's course in time).
 Prints one JSON object.
 """
 from __future__ import annotations
@@ -135,6 +137,48 @@ def errors(f, ref, fluid):
     return out
 
 
+def curve(case: str, every: int, steps: int | None = None, scale: float = 1.0, modes=None, mach: float | None = None,
+          log=None, plain_bgk: bool = False):
+    """All modes side by side from the same state: the relative L2 errors of
+    (rho, u, T) against FP64 every `every` steps, with the rms speed of the
+    FP64 field.  Returns {"columns": [...], "rows": [[step, ...], ...]}."""
+    import torch
+    make, default_modes, default_steps = CASES[case]
+    steps = default_steps if steps is None else steps
+    modes = [m for m in (default_modes if modes is None else modes) if m != "fp64"]
+    shape, solid, kw = make(scale) if mach is None else make(scale, mach)
+    if plain_bgk:
+        kw = dict(kw, kn_relax=False)
+    fluid = solid.reshape(-1) == 0
+    mask = solid if solid.any() else None
+    solvers = {"fp64": lbm.Solver(shape, solid=mask, storage="fp64", **kw)}
+    for m in modes:
+        storage, _, ref = m.partition("@")
+        solvers[m] = lbm.Solver(shape, solid=mask, storage=storage, shift_ref=int(ref == "stream"), **kw)
+    cols = ["step"] + [f"{m}_l2_{q}" for m in modes for q in ("rho", "u", "T")] + ["u_rms_fp64"]
+    rows = []
+    done = 0
+    while done < steps:
+        k = min(every, steps - done)
+        for s in solvers.values():
+            s.step(k)
+        done += k
+        ref, _ = solvers["fp64"].moments()
+        row = [done]
+        for m in modes:
+            e = errors(solvers[m].moments()[0], ref, fluid)
+            row += [e["l2_rho"], e["l2_u"], e["l2_T"]]
+        row.append(float(np.sqrt((ref[1:4, fluid] ** 2).sum(0).mean())))
+        rows.append(row)
+        if log:
+            log(" ".join(f"{c} {v:.3g}" for c, v in zip(cols, row)))
+    for s in solvers.values():
+        s.close()
+    torch.cuda.empty_cache()
+    return {"case": case, "shape": list(shape), "every": every, "steps": steps, "plain_bgk": plain_bgk,
+            "columns": cols, "rows": rows}
+
+
 def study(case: str, steps: int | None = None, scale: float = 1.0, modes=None, mach: float | None = None, log=None,
           plain_bgk: bool = False):
     make, default_modes, default_steps = CASES[case]
@@ -174,12 +218,19 @@ def main():
     ap.add_argument("--mach", type=float, default=None, help="default: the case's own (1.5; TGV 0.5)")
     ap.add_argument("--plain-bgk", action="store_true",
                     help="relax every cell with 1/tau (alpha(eps) off), in every mode including the FP64 reference")
+    ap.add_argument("--every", type=int, default=0,
+                    help="instead: run all modes side by side and report their errors every N steps")
     args = ap.parse_args()
     import torch
     if not torch.cuda.is_available():
         raise SystemExit("the precision study needs a GPU")
     torch.cuda.set_device(0)
     modes = args.modes.split(",") if args.modes else None
+    if args.every > 0:
+        res = curve(args.case, args.every, args.steps, args.scale, modes, args.mach,
+                    log=lambda m: print("#", m, file=sys.stderr, flush=True), plain_bgk=args.plain_bgk)
+        print(json.dumps(res), flush=True)
+        return
     res = study(args.case, args.steps, args.scale, modes, args.mach,
                 log=lambda m: print("#", m, file=sys.stderr, flush=True), plain_bgk=args.plain_bgk)
     print(json.dumps(res), flush=True)
