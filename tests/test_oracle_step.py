@@ -247,6 +247,54 @@ def test_shear_wave_decays_at_navier_stokes_rate(orc, T0, tau):
     assert abs(rate / (nu * k * k) - 1.0) < 0.01, rate / (nu * k * k)
 
 
+def _normal_response(c, T, du=1e-5):
+    """a(T) = d/du_x sum_i f^eq_i xi_x^3 at rest, per unit density, from
+    MINPACK equilibria (the Maxwellian's value is 3T)."""
+    fp = _equilibrium_minpack(c, 1.0, np.array([du, 0.0, 0.0]), T)
+    fm = _equilibrium_minpack(c, 1.0, np.array([-du, 0.0, 0.0]), T)
+    return float(((fp - fm) * c[:, 0] ** 3).sum() / (2 * du))
+
+
+def test_taylor_green_decays_at_the_lattice_rate(orc):
+    """3-D Taylor-Green vortex at small amplitude, in the linear regime.
+
+    Chapman-Enskog of the BGK step gives the viscous force
+    (tau - 1/2) d_b d_c (A_abcd u_d), with A_abcd = dQ^eq_abc / du_d at rest.
+    With cubic symmetry A has two values: a = dQ_xxx/du_x and the shear
+    response b = dQ_xxy/du_y of the shear-wave test.  For this field
+    (u_z = 0, div u = 0, every component an eigenfunction of the Laplacian
+    at -3k^2) the force on u_x reduces to -(tau - 1/2) a k^2 u_x, so the
+    kinetic energy decays at 2 (tau - 1/2) a k^2.  The Maxwellian has
+    a = 3b (an isotropic stress); the 13 constraints fix only the
+    contraction a + 2b = (D + 2) T, and on D3Q39 a is larger than 3b, so
+    this flow decays faster than the shear viscosity alone predicts.  Unlike
+    the 1-D shear wave, it checks streaming along y and z and the
+    off-diagonal moments of the equilibrium."""
+    n = 32
+    U, T0, tau = 1e-3, 0.5, 0.8
+    k = 2 * math.pi / n
+    rho, u, T = inputs.taylor_green_fields(n, U, T0)
+    o = orc.Oracle(n, n, n, gamma=1.4, tau=tau, kn_relax=False, newton_tol=1e-14)
+    assert o.init(rho, u, T) == 0
+
+    def energy():
+        m, _ = o.moments()
+        return 0.5 * float(np.mean(m[0] * (m[1] ** 2 + m[2] ** 2 + m[3] ** 2)))
+
+    o.step(10)  # past the start-up of the viscous stress
+    e1 = energy()
+    o.step(50)
+    e2 = energy()
+    c = orc.velocities().astype(np.float64)
+    a = _normal_response(c, T0)
+    b = _shear_response(c, T0)
+    assert abs(a + 2 * b - 5 * T0) < 1e-6  # the contracted third moment
+    assert a > 3.2 * b  # not the Maxwellian's 3b
+    rate = -math.log(e2 / e1) / 50
+    expected = 2 * (tau - 0.5) * a * k * k
+    assert abs(rate / expected - 1.0) < 0.01, (rate / expected, a / (3 * b))
+
+
 @pytest.mark.parametrize("gamma", [1.4, 1.3])
 def test_sound_speed(orc, gamma):
     """Adiabatic standing wave: the density at a node crosses its mean after a
