@@ -168,36 +168,44 @@ SERVING_MIX = dict(tube_cells=(200, 4000), box_cells=(64, 192), steps=(200, 2000
                    mach=(0.3, 1.5), reynolds=(1e3, 1e4))
 
 
-def serving_leg(count, rate, seed=2024, arena_gib=96, max_slots=64, graph_steps=32, sched="vft", sequential=True):
+def serving_leg(count, rate, seed=2024, arena_gib=96, max_slots=64, graph_steps=32, sched="vft", sequential=True,
+                batched=True):
     """The serving mix (seeded Poisson arrivals of tubes and boxes, FP32
     shifted storage): continuous batching in the pool against the same trace
     solved one at a time with the plain calls."""
-    import torch
     from paper_1910_13515_amd import inputs, serve
     trace = inputs.serving_trace(seed, count, rate, **SERVING_MIX)
-    pool = serve.Pool(arena_gib << 30, storage="fp32s", max_slots=max_slots, graph_steps=graph_steps, sched=sched)
-    # warm the graph and the admission path once (untimed)
-    warm = inputs.serving_trace(seed + 1, 2, 1e6, tube_cells=(200, 400), box_cells=(16, 16), steps=(40, 40))
-    serve.serve_batched(warm, pool, realtime=False)
+    out = {"trace": {"seed": seed, "requests": count, "rate_per_s": rate, "storage": "fp32s", **SERVING_MIX},
+           "pool": {"arena_gib": arena_gib, "max_slots": max_slots, "graph_steps": graph_steps, "sched": sched}}
+
     def progress(o, name):
         if o.rid % 20 == 19:
             print(f"# serving {name}: request {o.rid + 1} done at {o.done:.1f} s", file=sys.stderr, flush=True)
 
-    _, batched = serve.serve_batched(trace, pool, progress=lambda o: progress(o, "batched"))
-    pool.close()
-    del pool
-    torch.cuda.empty_cache()
-    print(f"# serving batched ({sched}): p50 {batched['p50_s']:.3f} s p99 {batched['p99_s']:.3f} s "
-          f"{batched['aggregate_glups']:.3f} GLUPS", file=sys.stderr, flush=True)
-    out = {"trace": {"seed": seed, "requests": count, "rate_per_s": rate, "storage": "fp32s", **SERVING_MIX},
-           "pool": {"arena_gib": arena_gib, "max_slots": max_slots, "graph_steps": graph_steps, "sched": sched},
-           "batched": batched}
+    if batched:
+        out["batched"] = _serve_pool(trace, seed, arena_gib, max_slots, graph_steps, sched, progress)
     if sequential:
         _, seq = serve.serve_sequential(trace, storage="fp32s", progress=lambda o: progress(o, "one at a time"))
         print(f"# serving one-at-a-time: p50 {seq['p50_s']:.3f} s p99 {seq['p99_s']:.3f} s "
               f"{seq['aggregate_glups']:.3f} GLUPS", file=sys.stderr, flush=True)
         out["one_at_a_time"] = seq
     return out
+
+
+def _serve_pool(trace, seed, arena_gib, max_slots, graph_steps, sched, progress):
+    import torch
+    from paper_1910_13515_amd import inputs, serve
+    pool = serve.Pool(arena_gib << 30, storage="fp32s", max_slots=max_slots, graph_steps=graph_steps, sched=sched)
+    # warm the graph and the admission path once (untimed)
+    warm = inputs.serving_trace(seed + 1, 2, 1e6, tube_cells=(200, 400), box_cells=(16, 16), steps=(40, 40))
+    serve.serve_batched(warm, pool, realtime=False)
+    _, batched = serve.serve_batched(trace, pool, progress=lambda o: progress(o, "batched"))
+    pool.close()
+    del pool
+    torch.cuda.empty_cache()
+    print(f"# serving batched ({sched}): p50 {batched['p50_s']:.3f} s p99 {batched['p99_s']:.3f} s "
+          f"{batched['aggregate_glups']:.3f} GLUPS", file=sys.stderr, flush=True)
+    return batched
 
 
 def cpu_baseline(seconds_target=15.0):
@@ -309,6 +317,8 @@ def main():
     ap.add_argument("--serving-rate", type=float, default=3.0)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-only", action="store_true")
+    ap.add_argument("--serving-side", default="both", choices=["both", "batched", "sequential"],
+                    help="with --serving-only: run one side of the comparison alone (for profiling)")
     ap.add_argument("--serving-sched", default="vft", choices=["vft", "srpt", "all"],
                     help="round selection of the pool (with --serving-only)")
     ap.add_argument("--cpu-table", action="store_true",
@@ -333,8 +343,9 @@ def main():
     from paper_1910_13515_amd import lbm
     lbm.load()
     if args.serving_only:
-        print(json.dumps({"serving": serving_leg(args.serving_requests, args.serving_rate, sched=args.serving_sched)}),
-              flush=True)
+        print(json.dumps({"serving": serving_leg(args.serving_requests, args.serving_rate, sched=args.serving_sched,
+                                                 batched=args.serving_side != "sequential",
+                                                 sequential=args.serving_side != "batched")}), flush=True)
         return
 
     main_res = run_mode(args.mode, args.n, args.steps, args.warmup)

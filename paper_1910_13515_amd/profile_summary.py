@@ -16,6 +16,10 @@ The counters are scaled by what they read for a plain device copy of known
 size (five copies of 1 GiB).
 
     python -m paper_1910_13515_amd.profile_summary <root> [--commands file]
+
+With --serving it instead summarises <root>/serve_batched and
+<root>/serve_sequential (kernel traces of the two sides of the serving leg)
+into ``profiles/serving_mix.md``.
 """
 from __future__ import annotations
 
@@ -204,11 +208,91 @@ def summarize(root, commands=None):
     return data
 
 
+def _dispatches(path):
+    """(name, start_ns, end_ns) of every kernel dispatch of a kernel trace."""
+    with open(path) as fh:
+        return [(r["Kernel_Name"], int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in csv.DictReader(fh)]
+
+
+def _union_ns(intervals):
+    """Length of the union of [start, end) intervals (kernels of two streams
+    may overlap in time)."""
+    total, cur_s, cur_e = 0, None, None
+    for s, e in sorted(intervals):
+        if cur_e is None or s > cur_e:
+            if cur_e is not None:
+                total += cur_e - cur_s
+            cur_s, cur_e = s, e
+        else:
+            cur_e = max(cur_e, e)
+    if cur_e is not None:
+        total += cur_e - cur_s
+    return total
+
+
+def serving_side(path):
+    """GPU activity of one side of the serving leg: step-kernel launches and
+    their durations, and how much of the span from the first to the last step
+    launch the device was busy (any kernel, and step kernels alone)."""
+    d = _dispatches(path)
+    steps = [(s, e) for n, s, e in d if "step_kernel" in n]
+    if not steps:
+        return None
+    t0 = min(s for s, _ in steps)
+    t1 = max(e for _, e in steps)
+    inside = [(max(s, t0), min(e, t1)) for _, s, e in d if e > t0 and s < t1]
+    durs = sorted(e - s for s, e in steps)
+    starts = sorted(s for s, _ in steps)
+    ends = sorted(e for _, e in steps)
+    gaps = sorted(max(0, b - a) for a, b in zip(ends[:-1], starts[1:]))
+    return {"step_launches": len(steps), "step_avg_us": sum(durs) / len(durs) / 1e3,
+            "step_p50_us": durs[len(durs) // 2] / 1e3, "step_max_us": durs[-1] / 1e3,
+            "span_s": (t1 - t0) / 1e9, "busy_any_s": _union_ns(inside) / 1e9, "busy_step_s": _union_ns(steps) / 1e9,
+            "busy_frac": _union_ns(inside) / (t1 - t0), "step_frac": _union_ns(steps) / (t1 - t0),
+            "gap_p50_us": gaps[len(gaps) // 2] / 1e3 if gaps else 0.0,
+            "other_kernels": len(inside) - len(steps)}
+
+
+def serving_summary(root, commands=None):
+    """profiles/serving_mix.md from <root>/serve_batched and <root>/serve_sequential."""
+    data = {}
+    for side in ("batched", "sequential"):
+        try:
+            data[side] = serving_side(_one(root, f"serve_{side}/**/*kernel_trace.csv"))
+        except FileNotFoundError:
+            data[side] = None
+    lines = ["# Serving mix: GPU activity of continuous batching against one solve at a time", "",
+             "rocprofv3 --kernel-trace of `bench.py --serving-only --serving-side <side>` (40 requests of the mix, "
+             "Poisson arrivals at 3/s, seed 2024, FP32-shifted storage), one run per side.  The span runs from the "
+             "first to the last step-kernel launch; busy time is the union of kernel intervals within it (the pool's "
+             "admission stream overlaps its rounds).  The batched side includes the pool's two-request warm-up.", "",
+             "| side | step launches | avg step (µs) | median step (µs) | max step (µs) | span (s) | busy, any kernel | "
+             "busy, step kernel | median gap between steps (µs) | other kernels |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
+    for side, r in data.items():
+        if r is None:
+            continue
+        lines.append(f"| {side} | {r['step_launches']} | {r['step_avg_us']:.1f} | {r['step_p50_us']:.1f} | "
+                     f"{r['step_max_us']:.1f} | {r['span_s']:.2f} | {r['busy_any_s']:.2f} s ({r['busy_frac']:.0%}) | "
+                     f"{r['busy_step_s']:.2f} s ({r['step_frac']:.0%}) | {r['gap_p50_us']:.1f} | {r['other_kernels']} |")
+    lines.append("")
+    if commands:
+        lines += ["Commands (run from the repository root on the GPU host, `cd /tmp && export TMPDIR=/tmp` first "
+                  "for the profiler):", "", "```"] + [ln.rstrip() for ln in open(commands) if ln.strip()] + ["```", ""]
+    with open(os.path.join(PROFILES, "serving_mix.md"), "w") as fh:
+        fh.write("\n".join(lines))
+    return data
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("root")
     ap.add_argument("--commands", default=None)
+    ap.add_argument("--serving", action="store_true", help="summarise the serving traces instead")
     args = ap.parse_args()
+    if args.serving:
+        print(json.dumps(serving_summary(args.root, args.commands), indent=1))
+        return
     print(json.dumps(summarize(args.root, args.commands), indent=1))
 
 
