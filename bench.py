@@ -326,8 +326,8 @@ def main():
     ap.add_argument("--cpu-table-short", action="store_true", help="with --cpu-table: the short set (Sod, TGV 32^3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the single-domain path is not sharded across GPUs "
-              "(see the multi-GPU design notes); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: a single domain is not sharded across GPUs here (x-slabs with "
+              "a 3-cell halo exchange would be the way); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.cpu_table:
         res = cpu_table(args.cpu_table_short, log=lambda m: print("#", m, file=sys.stderr, flush=True))
