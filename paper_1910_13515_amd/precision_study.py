@@ -88,15 +88,27 @@ CASES = {"airfoil": (airfoil_case, ("fp64", "fp32s"), 20000),
          "tgv": (tgv_case, ("fp64", "fp32s", "fp16s"), 1000)}
 
 
+def parse_mode(mode: str):
+    """(storage, shift_ref, newton_tol) of a mode string "storage[@stream][:tol]".
+    "@stream" stores deviations from the free stream's equilibrium instead of
+    the rest weights (shift_ref = 1); ":tol" overrides the Newton threshold
+    (0 = the storage mode's default)."""
+    base, _, tol = mode.partition(":")
+    storage, _, ref = base.partition("@")
+    if storage not in lbm.STORAGE or ref not in ("", "stream"):
+        raise ValueError(f"unknown mode {mode!r}")
+    if ref == "stream" and storage == "fp64":
+        raise ValueError("the stream shift applies to the shifted storage modes only")
+    return storage, int(ref == "stream"), float(tol) if tol else 0.0
+
+
 def run(shape, solid, kw, storage, steps, chunk=1000, log=None):
-    """Runs one mode; returns (fields[5, N], summary).  A mode "fp16s@stream"
-    (or "fp32s@stream") stores deviations from the free stream's equilibrium
-    instead of the rest weights (shift_ref = 1)."""
+    """Runs one mode (see parse_mode); returns (fields[5, N], summary)."""
     import torch
     mode = storage
-    storage, _, ref = mode.partition("@")
-    s = lbm.Solver(shape, solid=solid if solid.any() else None, storage=storage, shift_ref=int(ref == "stream"),
-                   **kw)
+    storage, shift_ref, tol = parse_mode(mode)
+    s = lbm.Solver(shape, solid=solid if solid.any() else None, storage=storage, shift_ref=shift_ref,
+                   **dict(kw, newton_tol=tol))
     info = s.info()
     t0 = time.perf_counter()
     failed = 0
@@ -118,7 +130,8 @@ def run(shape, solid, kw, storage, steps, chunk=1000, log=None):
     torch.cuda.empty_cache()
     upd = max(1, st.cell_updates)
     return fields, {
-        "storage": storage, "shift": "free stream" if ref == "stream" else "rest weights", "tau": info.tau, "seconds": dt, "glups": info.cells * steps / dt / 1e9,
+        "storage": storage, "shift": "free stream" if shift_ref else "rest weights", "newton_tol": tol,
+        "tau": info.tau, "seconds": dt, "glups": info.cells * steps / dt / 1e9,
         "newton_failures": int(failed), "newton_iterations_per_cell": st.iterations / upd,
         "newton_max_iterations": int(st.max_iterations),
         "alpha_fraction": [a / upd for a in st.alpha_hist], "totals": [float(v) for v in tot],
@@ -153,8 +166,8 @@ def curve(case: str, every: int, steps: int | None = None, scale: float = 1.0, m
     mask = solid if solid.any() else None
     solvers = {"fp64": lbm.Solver(shape, solid=mask, storage="fp64", **kw)}
     for m in modes:
-        storage, _, ref = m.partition("@")
-        solvers[m] = lbm.Solver(shape, solid=mask, storage=storage, shift_ref=int(ref == "stream"), **kw)
+        storage, shift_ref, tol = parse_mode(m)
+        solvers[m] = lbm.Solver(shape, solid=mask, storage=storage, shift_ref=shift_ref, **dict(kw, newton_tol=tol))
     cols = ["step"] + [f"{m}_l2_{q}" for m in modes for q in ("rho", "u", "T")] + ["u_rms_fp64"]
     rows = []
     done = 0
@@ -213,8 +226,9 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--modes", default=None,
-                    help="comma-separated subset of fp64,fp32s,fp16s; fp32s@stream and fp16s@stream shift the "
-                         "stored deviations by the free stream's equilibrium")
+                    help="comma-separated modes storage[@stream][:tol] with storage fp64, fp32s or fp16s; @stream "
+                         "shifts the stored deviations by the free stream's equilibrium, :tol sets the Newton "
+                         "threshold (fp64:1e-13 against fp64 gives the flow's round-off floor)")
     ap.add_argument("--mach", type=float, default=None, help="default: the case's own (1.5; TGV 0.5)")
     ap.add_argument("--plain-bgk", action="store_true",
                     help="relax every cell with 1/tau (alpha(eps) off), in every mode including the FP64 reference")

@@ -61,3 +61,15 @@ def test_relative_l2_errors():
     assert abs(e["l2_rho"] - 1e-3) < 1e-12
     assert e["l2_u"] == 0.0 and e["l2_T"] == 0.0
     assert abs(e["max_rho"] - np.max(np.abs(ref[0]) * 1e-3)) < 1e-15
+
+
+def test_precision_study_mode_strings():
+    import pytest
+    ps = precision_study
+    assert ps.parse_mode("fp64") == ("fp64", 0, 0.0)
+    assert ps.parse_mode("fp32s@stream") == ("fp32s", 1, 0.0)
+    assert ps.parse_mode("fp64:1e-13") == ("fp64", 0, 1e-13)
+    assert ps.parse_mode("fp16s@stream:2e-6") == ("fp16s", 1, 2e-6)
+    for bad in ("fp8", "fp32s@rest", "fp64@stream"):
+        with pytest.raises(ValueError):
+            ps.parse_mode(bad)
