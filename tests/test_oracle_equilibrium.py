@@ -246,3 +246,53 @@ def test_warm_start_converges_without_iterations(orc):
     feq2, _, lam2, it2 = orc.equilibrium(1.0, u, 0.5, lam=lam, tol=1e-13)
     assert it2 == 0
     np.testing.assert_array_equal(feq2, feq)
+
+
+def test_invariant_projection_weights_in_a_supersonic_stream(orc):
+    """The FP32 kernels remove the five collision-invariant residuals that the
+    Newton stop leaves by adding w_i (a + b.xi_i + c|xi_i|^2) with the rest
+    weights w_i.  In a Ma 1.5 stream at T = 2/3 the upstream populations are
+    1e-11..1e-8 while their rest weights are ~2e-3, so that correction swamps
+    them and the Knudsen sensor (Eq. eq:DeltaAvg) reads ~0.01-0.1 in a
+    uniform stream.  Weighting by the local equilibrium instead,
+    f^eq_i (a + b.xi_i + c|xi_i|^2) (a 5x5 solve with the equilibrium's own
+    moment matrix), removes the same residuals and leaves the sensor at the
+    level of the Newton stop.  Emulated in FP64 with the oracle's equilibria:
+    this pins the cause of the FP32 sensor inflation and the fix for it."""
+    c = orc.velocities().astype(np.float64)
+    q = (c ** 2).sum(1)
+    T = 2.0 / 3.0
+    u = np.array([1.5 * np.sqrt(1.4 * T), 0.0, 0.0])
+    fe, _, _, _ = orc.equilibrium(1.0, u, T, tol=1e-14, maxit=200)
+    w, _, _, _ = orc.equilibrium(1.0, np.zeros(3), T, tol=1e-14, maxit=200)
+    assert fe.min() < 1e-10 and w[np.argmin(fe)] > 1e-3
+    phi = np.stack([np.ones(39), c[:, 0], c[:, 1], c[:, 2], c[:, 0] ** 2, c[:, 1] ** 2, c[:, 2] ** 2], 1)
+    target = np.array([1.0, u[0], 0.0, 0.0, u[0] ** 2 + T, T, T])
+    inv5 = np.stack([np.ones(39), c[:, 0], c[:, 1], c[:, 2], q], 1)  # mass, momentum, energy
+    # the rest-weight projection's constants, as the library derives them
+    W0, Wq, Wqq, W2 = w.sum(), (w * q).sum(), (w * q * q).sum(), (w * c[:, 0] ** 2).sum()
+    det = W0 * Wqq - Wq * Wq
+    rng = np.random.default_rng(5)
+    eps_rest, eps_local, eps_none = [], [], []
+    for _ in range(12):
+        # warm start from a neighbouring state's multipliers, stopped at the FP32 threshold
+        _, _, lam_prev, _ = orc.equilibrium(1.0, u + 1e-3 * rng.standard_normal(3),
+                                            T * (1 + 1e-3 * rng.standard_normal()), tol=1e-14, maxit=200)
+        fs, _, _, _ = orc.equilibrium(1.0, u, T, lam=lam_prev, tol=1e-5, maxit=20)
+        G = fs @ phi - target
+        r = np.array([G[0], G[1], G[2], G[3], G[4] + G[5] + G[6]])
+        a = -(Wqq * r[0] - Wq * r[4]) / det
+        cc = -(-Wq * r[0] + W0 * r[4]) / det
+        b = -r[1:4] / W2
+        f_rest = fs + w * (a + c @ b + cc * q)
+        x = np.linalg.solve((inv5 * fs[:, None]).T @ inv5, -r)
+        f_local = fs + fs * (inv5 @ x)
+        # both remove the invariant residuals (to first order in them)
+        for fp in (f_rest, f_local):
+            assert np.max(np.abs(fp @ inv5 - np.array([1.0, u[0], 0.0, 0.0, u[0] ** 2 + 3 * T]))) < 1e-9
+        eps_none.append(np.mean(np.abs(fe - fs) / fs))
+        eps_rest.append(np.mean(np.abs(fe - f_rest) / np.abs(f_rest)))
+        eps_local.append(np.mean(np.abs(fe - f_local) / f_local))
+    assert np.median(eps_none) < 1e-4
+    assert np.median(eps_rest) > 1e-2           # the sensor fires in a uniform stream
+    assert np.median(eps_local) < 1e-4          # it does not with local weights
