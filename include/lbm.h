@@ -54,6 +54,15 @@ typedef enum {
     LBM_E_NONFINITE = -6       /* a moment is NaN or infinite */
 } lbm_status;
 
+/* The shifted modes stop Newton at 1e-5 of the largest target (FP32
+ * arithmetic) and then remove the five collision-invariant residuals with a
+ * correction proportional to the rest-state weights, so that mass, momentum
+ * and energy are conserved.  Far from rest (a supersonic stream) that
+ * correction is large against the smallest equilibrium populations, and the
+ * Knudsen sensor of Eq. (eq:DeltaAvg) reads high there: more cells take the
+ * stronger relaxation branches of Eq. (eq:alpha) than in FP64.  The moments
+ * stay within the FP64 run's own round-off sensitivity on the supersonic
+ * airfoil and sphere flows. */
 typedef enum {
     LBM_STORE_FP64 = 0,          /* populations and multipliers in FP64, arithmetic in FP64 */
     LBM_STORE_FP32_SHIFTED = 1,  /* populations stored in FP32 as deviations from shift weights, FP32 arithmetic */
