@@ -60,6 +60,7 @@ class _Params(ctypes.Structure):
         ("faces", ctypes.c_int32 * 6),
         ("gamma", ctypes.c_double), ("tau", ctypes.c_double), ("newton_tol", ctypes.c_double),
         ("solid", ctypes.c_void_p),
+        ("floor_rule", ctypes.c_int32), ("skip_cold_after_failure", ctypes.c_int32),
     ]
 
 
@@ -67,7 +68,7 @@ class Stats(ctypes.Structure):
     _fields_ = [
         ("iterations", ctypes.c_int64), ("max_iterations", ctypes.c_int64),
         ("failed", ctypes.c_int64), ("alpha_hist", ctypes.c_int64 * 4),
-        ("cold_restarts", ctypes.c_int64),
+        ("cold_restarts", ctypes.c_int64), ("evaluations", ctypes.c_int64),
     ]
 
 
@@ -144,7 +145,8 @@ class Oracle:
     multipliers lam, SoA ``[39][N]`` / ``[13][N]`` with x fastest)."""
 
     def __init__(self, nx, ny, nz, gamma=1.4, tau=0.6, kn_relax=True, faces=(0,) * 6, solid=None,
-                 newton_tol=1e-13, newton_maxit=30, variant="plain"):
+                 newton_tol=1e-13, newton_maxit=30, variant="plain", floor_rule=True,
+                 skip_cold_after_failure=True):
         self.L = lib(variant)
         self.shape = (nx, ny, nz)
         self.n = nx * ny * nz
@@ -163,6 +165,8 @@ class Oracle:
         p.tau = self.tau
         p.newton_tol = float(newton_tol)
         p.solid = _ptr(self.solid) if self.solid is not None else None
+        p.floor_rule = int(bool(floor_rule))
+        p.skip_cold_after_failure = int(bool(skip_cold_after_failure))
         self.p = p
         self.f = np.zeros(NQ * self.n)
         self.g = np.zeros(NQ * self.n)
@@ -202,6 +206,7 @@ class Oracle:
             tot.max_iterations = max(tot.max_iterations, st.max_iterations)
             tot.failed += st.failed
             tot.cold_restarts += st.cold_restarts
+            tot.evaluations += st.evaluations
             for k in range(4):
                 tot.alpha_hist[k] += st.alpha_hist[k]
         self.stats = tot

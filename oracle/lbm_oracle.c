@@ -200,18 +200,12 @@ static double norm_2(const double v[NL])
     return sqrt(r);
 }
 
-/* Cold start of the multipliers at t = 0 (reading: the paper only gives the
- * warm start from t - 1): the Maxwellian shape lambda_1 = u/T,
- * lambda_2 = -delta/(2T), lambda_3 = 0, lambda_0 normalising the sum to 1. */
-static void cold_guess(const double u[3], double T, double lam[NL])
+/* lambda_0 that normalises sum_i exp(phi_i . lambda) to 1 for the other 12
+ * multipliers. */
+static void normalise(double lam[NL])
 {
     double s = 0.0;
     int i, k;
-    for (k = 0; k < NL; ++k) lam[k] = 0.0;
-    lam[1] = u[0] / T;
-    lam[2] = u[1] / T;
-    lam[3] = u[2] / T;
-    lam[4] = lam[5] = lam[6] = -0.5 / T;
     for (i = 0; i < NQ; ++i) {
         double e = 0.0;
         for (k = 1; k < NL; ++k) e += PHI[i][k] * lam[k];
@@ -220,60 +214,85 @@ static void cold_guess(const double u[3], double T, double lam[NL])
     lam[0] = -log(s);
 }
 
+/* Cold start of the multipliers at t = 0 (reading: the paper only gives the
+ * warm start from t - 1): the Maxwellian shape lambda_1 = u/T,
+ * lambda_2 = -delta/(2T), lambda_3 = 0, lambda_0 normalising the sum to 1. */
+static void cold_guess(const double u[3], double T, double lam[NL])
+{
+    int k;
+    for (k = 0; k < NL; ++k) lam[k] = 0.0;
+    lam[1] = u[0] / T;
+    lam[2] = u[1] / T;
+    lam[3] = u[2] / T;
+    lam[4] = lam[5] = lam[6] = -0.5 / T;
+    normalise(lam);
+}
+
 /* Newton-Raphson for the 13 multipliers (Sec. 5 algorithm table): evaluate
  * f^eq and G; stop when the error norm is below tol; otherwise build J, solve,
  * and step.  Reading of the stopping norm: max_k |G_k| / rho <=
  * tol * max(1, max_k |M_k| / rho).  Globalisation (reading; the paper says
  * only "standard multivariate Newton-Raphson"): the step is halved while the
- * Euclidean norm of G does not decrease; if the full step does not decrease
- * it while max_k |G_k| before and after it is within 8 times the bound, the
- * step is taken and the solve stops (round-off floor).  On return lam and feq (per unit density) hold the last
- * iterate.  Returns the number of accepted updates,
- * or -1 when the cap is reached, J is not positive definite, or a value is
- * not finite. */
-static int newton(const double m[NL], double lam[NL], double feq[NQ], double tol, int maxit)
+ * Euclidean norm of G does not decrease, trying t = 1, 1/2, ..., 2^-39.
+ * Round-off floor (reading, switch floor_rule): if the full step does not
+ * lower the norm while max_k |G_k| before and after it is within 8 times the
+ * bound, the step is taken and the solve stops.  Stall (reading): when no
+ * trial lowers the norm, the attempt fails (no descent is left along the
+ * Newton direction, which happens where no multipliers satisfy the
+ * constraints).  On return lam and feq (per unit density) hold the last
+ * iterate and *evals (if not NULL) has been increased by the number of f^eq
+ * evaluations.  Returns the number of accepted updates, or -1 when the cap
+ * is reached, J is not positive definite, a value is not finite, or the line
+ * search stalls. */
+static int newton(const double m[NL], double lam[NL], double feq[NQ], double tol, int maxit, int floor_rule,
+                  int64_t *evals)
 {
     double G[NL], J[NL][NL], d[NL], trial[NL], Gt[NL], ft[NQ];
     double scale = 1.0;
     int it, k, ls;
+    int64_t ne = 1;
     for (k = 0; k < NL; ++k)
         if (fabs(m[k]) > scale) scale = fabs(m[k]);
     equilibrium_and_residual(lam, m, feq, G);
     for (it = 0;; ++it) {
         double r = norm_inf(G);
-        double n0;
-        if (!isfinite(r)) return -1;
-        if (r <= tol * scale) return it;
-        if (it >= maxit) return -1;
+        double n0, t = 1.0;
+        int descended = 0;
+        if (!isfinite(r)) break;
+        if (r <= tol * scale) {
+            if (evals) *evals += ne;
+            return it;
+        }
+        if (it >= maxit) break;
         jacobian(feq, J);
-        if (cholesky_solve(J, G, d) != 0) return -1;
+        if (cholesky_solve(J, G, d) != 0) break;
         n0 = norm_2(G);
-        {
-            double t = 1.0;
-            /* reading: when the full step does not lower the residual while
-             * the iterate and the step's end are both within 8 times the
-             * tolerance, the residual sits at the round-off floor of the
-             * arithmetic; the step is taken and the solve stops */
-            for (k = 0; k < NL; ++k) trial[k] = lam[k] - d[k];
+        for (ls = 0; ls < 40; ++ls) {
+            for (k = 0; k < NL; ++k) trial[k] = lam[k] - t * d[k];
             equilibrium_and_residual(trial, m, ft, Gt);
-            if (!(norm_2(Gt) < n0) && r <= 8.0 * tol * scale && norm_inf(Gt) <= 8.0 * tol * scale) {
+            ne += 1;
+            if (norm_2(Gt) < n0) {
+                descended = 1;
+                break;
+            }
+            if (ls == 0 && floor_rule && r <= 8.0 * tol * scale && norm_inf(Gt) <= 8.0 * tol * scale) {
+                /* the residual sits at the round-off floor of the arithmetic */
                 for (k = 0; k < NL; ++k) lam[k] = trial[k];
                 for (k = 0; k < NQ; ++k) feq[k] = ft[k];
+                if (evals) *evals += ne;
                 return it + 1;
             }
-            for (ls = 0; ls < 40; ++ls) {
-                for (k = 0; k < NL; ++k) trial[k] = lam[k] - t * d[k];
-                equilibrium_and_residual(trial, m, ft, Gt);
-                if (norm_2(Gt) < n0) break;
-                t *= 0.5;
-            }
+            t *= 0.5;
         }
+        if (!descended) break;
         for (k = 0; k < NL; ++k) {
             lam[k] = trial[k];
             G[k] = Gt[k];
         }
         for (k = 0; k < NQ; ++k) feq[k] = ft[k];
     }
+    if (evals) *evals += ne;
+    return -1;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -292,6 +311,9 @@ typedef struct {
     double tau;
     double newton_tol;
     const uint8_t *solid;  /* nx*ny*nz or NULL */
+    /* readings that the pins switch off to show what they change (1 = on) */
+    int32_t floor_rule;    /* stop at the round-off floor (see newton) */
+    int32_t skip_cold_after_failure; /* a cell that failed the previous step is not restarted cold */
 } orc_params;
 
 typedef struct {
@@ -300,6 +322,7 @@ typedef struct {
     int64_t failed;        /* cells whose Newton did not converge */
     int64_t alpha_hist[4]; /* cells per branch of Eq. (eq:alpha) */
     int64_t cold_restarts; /* cells that fell back to the cold start */
+    int64_t evaluations;   /* f^eq evaluations of the Newton solves (line-search trials included) */
 } orc_stats;
 
 void orc_velocities(int32_t *out)
@@ -326,7 +349,7 @@ int orc_equilibrium(double rho, const double *u, double T, double gamma, double 
     make_tables();
     mb_targets(u, T, m);
     if (cold) cold_guess(u, T, lam);
-    it = newton(m, lam, feq, tol, maxit);
+    it = newton(m, lam, feq, tol, maxit, 1, NULL);
     for (i = 0; i < NQ; ++i) {
         if (feq_out) feq_out[i] = rho * feq[i];
         if (geq_out) geq_out[i] = delta * T * rho * feq[i];
@@ -510,26 +533,28 @@ int64_t orc_init(const orc_params *p, const double *rho, const double *u, const 
  * relaxation factor, and write the BGK-relaxed populations.  Boundary and
  * solid cells are copied unchanged.  A fluid cell whose Newton solve fails
  * (warm start, then cold start) is not collided: its gathered populations are
- * written unchanged and its multipliers kept; it is counted in st->failed and
- * in no alpha branch.  iters_out / eps_out (length N, or NULL) receive
- * per-cell diagnostics (-1 / NaN outside fluid cells, NaN for eps of a failed
- * cell). */
+ * written unchanged and its multipliers kept, with lambda_0 replaced by NaN
+ * as the mark of the failure; it is counted in st->failed and in no alpha
+ * branch.  A marked cell warm-starts from its other 12 multipliers
+ * (lambda_0 normalising) and, with skip_cold_after_failure, is not restarted
+ * cold.  iters_out / eps_out (length N, or NULL) receive per-cell
+ * diagnostics (-1 / NaN outside fluid cells, NaN for eps of a failed cell). */
 void orc_step(const orc_params *p, const double *f, const double *g, const double *lam, double *fo, double *go,
               double *lamo, int32_t *iters_out, double *eps_out, orc_stats *st)
 {
     int64_t n = (int64_t)p->nx * p->ny * p->nz;
     int64_t c;
-    int64_t s_it = 0, s_max = 0, s_fail = 0, s_cold = 0, h0 = 0, h1 = 0, h2 = 0, h3 = 0;
+    int64_t s_it = 0, s_max = 0, s_fail = 0, s_cold = 0, h0 = 0, h1 = 0, h2 = 0, h3 = 0, s_ev = 0;
     double Cv = heat_capacity(p->gamma);
     double delta = 2.0 * Cv - DIM;
     make_tables();
 #pragma omp parallel for schedule(dynamic, 64) \
-    reduction(+ : s_it, s_fail, s_cold, h0, h1, h2, h3) reduction(max : s_max)
+    reduction(+ : s_it, s_fail, s_cold, h0, h1, h2, h3, s_ev) reduction(max : s_max)
     for (c = 0; c < n; ++c) {
         int x = (int)(c % p->nx);
         int y = (int)((c / p->nx) % p->ny);
         int z = (int)(c / ((int64_t)p->nx * p->ny));
-        int i, k, it, br, bounced;
+        int i, k, it, br, bounced, marked;
         double fi[NQ], gi[NQ], l[NL], m[NL], feq[NQ], geq[NQ];
         double rho, u[3], T, eps, tau_eff, omega;
         if (cell_type(p, x, y, z) != CELL_FLUID) {
@@ -554,14 +579,21 @@ void orc_step(const orc_params *p, const double *f, const double *g, const doubl
         mb_targets(u, T, m);
         /* multipliers: warm start from the previous step */
         for (k = 0; k < NL; ++k) l[k] = lam[k * n + c];
-        it = newton(m, l, feq, p->newton_tol, p->newton_maxit);
+        marked = isnan(l[0]);
+        if (marked) normalise(l);
+        it = newton(m, l, feq, p->newton_tol, p->newton_maxit, p->floor_rule, &s_ev);
         if (it < 0) {
             /* reading: a failed warm start is retried once from the cold
-             * start before the cell is counted as failed */
-            int it2;
-            s_cold += 1;
-            cold_guess(u, T, l);
-            it2 = newton(m, l, feq, p->newton_tol, p->newton_maxit > 100 ? p->newton_maxit : 100);
+             * start before the cell is counted as failed, unless the cell
+             * also failed the previous step (then the retry is skipped, which
+             * bounds the cost of a cell that has no equilibrium) */
+            int it2 = -1;
+            if (!(marked && p->skip_cold_after_failure)) {
+                s_cold += 1;
+                cold_guess(u, T, l);
+                it2 = newton(m, l, feq, p->newton_tol, p->newton_maxit > 100 ? p->newton_maxit : 100,
+                             p->floor_rule, &s_ev);
+            }
             if (it2 < 0) {
                 /* reading: where no multipliers reproduce the 13 targets the
                  * cell is not collided; its gathered populations are stored
@@ -575,6 +607,7 @@ void orc_step(const orc_params *p, const double *f, const double *g, const doubl
                     go[i * n + c] = gi[i];
                 }
                 for (k = 0; k < NL; ++k) lamo[k * n + c] = lam[k * n + c];
+                lamo[c] = NAN;
                 if (iters_out) iters_out[c] = p->newton_maxit;
                 if (eps_out) eps_out[c] = NAN;
                 continue;
@@ -616,6 +649,7 @@ void orc_step(const orc_params *p, const double *f, const double *g, const doubl
         st->max_iterations = s_max;
         st->failed = s_fail;
         st->cold_restarts = s_cold;
+        st->evaluations = s_ev;
         st->alpha_hist[0] = h0;
         st->alpha_hist[1] = h1;
         st->alpha_hist[2] = h2;

@@ -249,16 +249,17 @@ def test_warm_start_converges_without_iterations(orc):
 
 
 def test_invariant_projection_weights_in_a_supersonic_stream(orc):
-    """The FP32 kernels remove the five collision-invariant residuals that the
-    Newton stop leaves by adding w_i (a + b.xi_i + c|xi_i|^2) with the rest
-    weights w_i.  In a Ma 1.5 stream at T = 2/3 the upstream populations are
-    1e-11..1e-8 while their rest weights are ~2e-3, so that correction swamps
-    them and the Knudsen sensor (Eq. eq:DeltaAvg) reads ~0.01-0.1 in a
-    uniform stream.  Weighting by the local equilibrium instead,
-    f^eq_i (a + b.xi_i + c|xi_i|^2) (a 5x5 solve with the equilibrium's own
-    moment matrix), removes the same residuals and leaves the sensor at the
-    level of the Newton stop.  Emulated in FP64 with the oracle's equilibria:
-    this pins the cause of the FP32 sensor inflation and the fix for it."""
+    """Reduced-precision solves stop at a tolerance far above FP64's, so the
+    five collision-invariant residuals they leave are projected out of f^eq.
+    With rest-state weights, f_i += w_i (a + b.xi_i + c|xi_i|^2), a Ma 1.5
+    stream at T = 2/3 breaks: its upstream populations are 1e-11..1e-8 while
+    their rest weights are ~2e-3, so the correction swamps them (some turn
+    negative) and the Knudsen sensor (Eq. eq:DeltaAvg), with the kernel's
+    division by the signed f^eq, reads far from its true value in a uniform
+    stream.  Weighting by the local equilibrium, f_i (1 + x.psi_i) with
+    M x = -R and M = sum_i f_i psi_i psi_i^T (psi = 1, xi, |xi|^2), removes
+    the same residuals exactly and keeps the sensor at the level of the
+    Newton stop, also when the 5x5 solve runs in FP32 as in the kernels."""
     c = orc.velocities().astype(np.float64)
     q = (c ** 2).sum(1)
     T = 2.0 / 3.0
@@ -266,33 +267,47 @@ def test_invariant_projection_weights_in_a_supersonic_stream(orc):
     fe, _, _, _ = orc.equilibrium(1.0, u, T, tol=1e-14, maxit=200)
     w, _, _, _ = orc.equilibrium(1.0, np.zeros(3), T, tol=1e-14, maxit=200)
     assert fe.min() < 1e-10 and w[np.argmin(fe)] > 1e-3
-    phi = np.stack([np.ones(39), c[:, 0], c[:, 1], c[:, 2], c[:, 0] ** 2, c[:, 1] ** 2, c[:, 2] ** 2], 1)
-    target = np.array([1.0, u[0], 0.0, 0.0, u[0] ** 2 + T, T, T])
-    inv5 = np.stack([np.ones(39), c[:, 0], c[:, 1], c[:, 2], q], 1)  # mass, momentum, energy
-    # the rest-weight projection's constants, as the library derives them
+    psi = np.stack([np.ones(39), c[:, 0], c[:, 1], c[:, 2], q], 1)  # mass, momentum, energy
+    target5 = np.array([1.0, u[0], 0.0, 0.0, u[0] ** 2 + 3 * T])
+    # the rest-weight projection's constants
     W0, Wq, Wqq, W2 = w.sum(), (w * q).sum(), (w * q * q).sum(), (w * c[:, 0] ** 2).sum()
     det = W0 * Wqq - Wq * Wq
     rng = np.random.default_rng(5)
-    eps_rest, eps_local, eps_none = [], [], []
+    eps_rest, eps_local, eps_local32, eps_none, min_rest, min_local = [], [], [], [], [], []
     for _ in range(12):
         # warm start from a neighbouring state's multipliers, stopped at the FP32 threshold
         _, _, lam_prev, _ = orc.equilibrium(1.0, u + 1e-3 * rng.standard_normal(3),
                                             T * (1 + 1e-3 * rng.standard_normal()), tol=1e-14, maxit=200)
         fs, _, _, _ = orc.equilibrium(1.0, u, T, lam=lam_prev, tol=1e-5, maxit=20)
-        G = fs @ phi - target
-        r = np.array([G[0], G[1], G[2], G[3], G[4] + G[5] + G[6]])
+        r = fs @ psi - target5
+        assert np.max(np.abs(r)) > 1e-9  # the stop leaves residuals to remove
         a = -(Wqq * r[0] - Wq * r[4]) / det
         cc = -(-Wq * r[0] + W0 * r[4]) / det
         b = -r[1:4] / W2
         f_rest = fs + w * (a + c @ b + cc * q)
-        x = np.linalg.solve((inv5 * fs[:, None]).T @ inv5, -r)
-        f_local = fs + fs * (inv5 @ x)
-        # both remove the invariant residuals (to first order in them)
-        for fp in (f_rest, f_local):
-            assert np.max(np.abs(fp @ inv5 - np.array([1.0, u[0], 0.0, 0.0, u[0] ** 2 + 3 * T]))) < 1e-9
+        x = np.linalg.solve((psi * fs[:, None]).T @ psi, -r)
+        f_local = fs * (1.0 + psi @ x)
+        # the same in FP32 arithmetic
+        f32 = fs.astype(np.float32)
+        p32 = psi.astype(np.float32)
+        x32 = np.linalg.solve((p32 * f32[:, None]).T @ p32, -(f32 @ p32 - target5.astype(np.float32)))
+        f_local32 = (f32 * (np.float32(1) + p32 @ x32)).astype(np.float64)
+        # both remove the invariant residuals
+        assert np.max(np.abs(f_rest @ psi - target5)) < 1e-9
+        assert np.max(np.abs(f_local @ psi - target5)) < 1e-12
         eps_none.append(np.mean(np.abs(fe - fs) / fs))
-        eps_rest.append(np.mean(np.abs(fe - f_rest) / np.abs(f_rest)))
+        # the kernel's sensor: |f - f^eq| times the reciprocal of the signed f^eq
+        eps_rest.append(np.mean(np.abs(fe - f_rest) / f_rest))
         eps_local.append(np.mean(np.abs(fe - f_local) / f_local))
+        eps_local32.append(np.mean(np.abs(fe - f_local32) / f_local32))
+        min_rest.append(f_rest.min())
+        min_local.append(min(f_local.min(), f_local32.min()))
     assert np.median(eps_none) < 1e-4
-    assert np.median(eps_rest) > 1e-2           # the sensor fires in a uniform stream
-    assert np.median(eps_local) < 1e-4          # it does not with local weights
+    # cause: rest weights drive small equilibria negative and the sensor off
+    assert min(min_rest) < 0.0
+    assert np.max(np.abs(np.array(eps_rest))) > 1e-2
+    # fix: local weights keep every population positive and the sensor at
+    # the level of the Newton stop, in FP64 and FP32 arithmetic alike
+    assert min(min_local) > 0.0
+    assert max(eps_local) < 1e-4
+    assert max(eps_local32) < 1e-4

@@ -499,10 +499,223 @@ def test_cell_without_equilibrium_is_not_collided(orc):
     gs = orc.Oracle(*shape, gamma=1.4, tau=0.6).stream_only(G.reshape(-1)).reshape(39, n)
     np.testing.assert_array_equal(o.f.reshape(39, n)[:, failed], fs[:, failed])
     np.testing.assert_array_equal(o.g.reshape(39, n)[:, failed], gs[:, failed])
-    np.testing.assert_array_equal(o.lam.reshape(13, n)[:, failed], lam.reshape(13, n)[:, failed])
+    # the multipliers are kept, lambda_0 marked NaN (the failure mark)
+    np.testing.assert_array_equal(o.lam.reshape(13, n)[1:, failed], lam.reshape(13, n)[1:, failed])
+    assert np.isnan(o.lam.reshape(13, n)[0, failed]).all()
+    assert not np.isnan(o.lam.reshape(13, n)[0, ~failed]).any()
     assert np.all(iters[failed] == o.p.newton_maxit)
     # the collided cells differ from their gathered values
     assert np.max(np.abs(o.f.reshape(39, n)[:, ~failed] - fs[:, ~failed])) > 1e-6
     _, t1 = o.moments()
     assert abs(t1[0] - t0[0]) <= 1e-13 * t0[0]
     assert abs(t1[4] - t0[4]) <= 1e-12 * t0[4]
+
+
+def _brute_step_open(c, f, g, shape, faces, solid, tau, gamma, kn_relax):
+    """One step written out cell by cell for grids with open faces and an
+    obstacle (Sec. 4 set-up): (i) every cell inside a Neumann face's three
+    layers first receives a copy of the interior cell it faces (its
+    coordinate clamped to the nearest interior layer along every Neumann
+    axis); (ii) fluid cells pull h_i(x - xi_i), wrapping periodic axes only;
+    (iii) a link is blocked when a node on the walk x - k xi_i / m,
+    k = 1..m (m = the largest component of xi_i) is solid, and then the cell
+    takes its own population of the opposite velocity; (iv) the collision
+    with a MINPACK equilibrium and the relaxation table.  Cells in the
+    equilibrium layers and solid cells keep their values.  Returns the new
+    f, g (fluid cells) and the fluid mask."""
+    nx, ny, nz = shape
+    dims = (nx, ny, nz)
+    f = f.reshape(39, nz, ny, nx).copy()
+    g = g.reshape(39, nz, ny, nx).copy()
+    sol = solid.reshape(nz, ny, nx).astype(bool)
+    EQ, NEU = 1, 2
+    ci = c.astype(int)
+    opp = [int(np.flatnonzero((ci == -ci[i]).all(1))[0]) for i in range(39)]
+
+    def in_layer(coord, kind):
+        return any((faces[2 * a] == kind and coord[a] < 3) or (faces[2 * a + 1] == kind and coord[a] >= dims[a] - 3)
+                   for a in range(3))
+
+    # (i) Neumann layers hold copies of the interior
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                cc = [x, y, z]
+                if not in_layer(cc, NEU):
+                    continue
+                src = list(cc)
+                for a in range(3):
+                    if faces[2 * a] == NEU and src[a] < 3:
+                        src[a] = 3
+                    if faces[2 * a + 1] == NEU and src[a] >= dims[a] - 3:
+                        src[a] = dims[a] - 4
+                f[:, z, y, x] = f[:, src[2], src[1], src[0]]
+                g[:, z, y, x] = g[:, src[2], src[1], src[0]]
+    Cv = 1.0 / (gamma - 1.0)
+    bounds, taus = _alpha_table(tau)
+    fo = f.copy()
+    go = g.copy()
+    fluid = np.zeros((nz, ny, nx), dtype=bool)
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                if sol[z, y, x] or in_layer([x, y, z], EQ) or in_layer([x, y, z], NEU):
+                    continue
+                fluid[z, y, x] = True
+                fi = np.empty(39)
+                gi = np.empty(39)
+                for i in range(39):
+                    m = int(np.abs(ci[i]).max())
+                    blocked = False
+                    for k in range(1, m + 1):
+                        p = [x - k * ci[i, 0] // m, y - k * ci[i, 1] // m, z - k * ci[i, 2] // m]
+                        p = [p[a] % dims[a] if faces[2 * a] == 0 else p[a] for a in range(3)]
+                        if sol[p[2], p[1], p[0]]:
+                            blocked = True
+                            break
+                    if blocked:
+                        fi[i] = f[opp[i], z, y, x]
+                        gi[i] = g[opp[i], z, y, x]
+                    else:
+                        s = [x - ci[i, 0], y - ci[i, 1], z - ci[i, 2]]
+                        s = [s[a] % dims[a] if faces[2 * a] == 0 else s[a] for a in range(3)]
+                        fi[i] = f[i, s[2], s[1], s[0]]
+                        gi[i] = g[i, s[2], s[1], s[0]]
+                rho = fi.sum()
+                u = (fi[:, None] * c).sum(0) / rho
+                e = (fi * (c ** 2).sum(1)).sum() + gi.sum()
+                T = (e - rho * (u @ u)) / (2 * Cv * rho)
+                feq = _equilibrium_minpack(c, rho, u, T)
+                geq = (2 * Cv - 3) * T * feq
+                eps = np.mean(np.abs(fi - feq) / feq)
+                b = max(k for k in range(4) if eps >= bounds[k]) if kn_relax else 0
+                fo[:, z, y, x] = fi - (fi - feq) / taus[b]
+                go[:, z, y, x] = gi - (gi - geq) / taus[b]
+    return fo.reshape(39, -1), go.reshape(39, -1), fluid.reshape(-1)
+
+
+def test_brute_force_open_faces_and_obstacle(orc):
+    """One step on a grid with every face kind (equilibrium low x and high y,
+    Neumann high x and low y, periodic z) and a solid block that touches a
+    Neumann layer, against the explicit cell-by-cell step above: pins the
+    Neumann pull (the oracle redirects reads into the layers, the brute
+    force copies the interior into them first), the frozen equilibrium
+    layers and multi-speed bounce-back."""
+    shape = (14, 12, 4)
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    gamma, tau = 1.4, 0.58
+    c = orc.velocities().astype(np.float64)
+    faces = (orc.FACE_EQUILIBRIUM, orc.FACE_NEUMANN, orc.FACE_NEUMANN, orc.FACE_EQUILIBRIUM, 0, 0)
+    solid = np.zeros((nz, ny, nx), dtype=np.uint8)
+    solid[1:3, 5:7, 6:8] = 1        # interior block
+    solid[0:2, 3, 9] = 1            # next to the low-y Neumann layer
+    rho, u, T = inputs.random_fields(shape, seed=21, rho=(0.9, 1.1), umax=0.2, T=(0.45, 0.55))
+    u = u.reshape(3, n)
+    u[0] += 0.15                    # a mean stream through the open faces
+    pert = inputs.random_perturbation(shape, seed=22, amplitudes=(0.05,))
+    o = orc.Oracle(*shape, gamma=gamma, tau=tau, kn_relax=True, faces=faces, solid=solid.ravel(),
+                   newton_tol=1e-14, newton_maxit=50)
+    assert o.init(rho, u.reshape(-1), T) == 0
+    f = o.f * np.exp(pert[0].reshape(-1))
+    g = o.g * np.exp(pert[1].reshape(-1))
+    o.set_state(f, g, o.lam)
+    o.step(1)
+    assert o.stats.failed == 0
+    fb, gb, fluid = _brute_step_open(c, f, g, shape, faces, solid.ravel(), tau, gamma, True)
+    types = o.cell_types()
+    np.testing.assert_array_equal(fluid, types == orc.CELL_FLUID)
+    F, G = o.f.reshape(39, n), o.g.reshape(39, n)
+    assert np.max(np.abs(F[:, fluid] - fb[:, fluid])) <= 1e-12 * np.abs(fb[:, fluid]).max()
+    assert np.max(np.abs(G[:, fluid] - gb[:, fluid])) <= 1e-12 * np.abs(gb[:, fluid]).max()
+    # boundary and solid cells are not updated by the step
+    np.testing.assert_array_equal(F[:, ~fluid], f.reshape(39, n)[:, ~fluid])
+    # the step really exercised bounce-back next to the block and reads from
+    # the Neumann layers (fluid cells within 3 cells of them)
+    assert solid.sum() == 10 and fluid.reshape(nz, ny, nx)[:, 3:6, :].any()
+
+
+@pytest.mark.parametrize("tol", [1e-12, 1e-14])
+@pytest.mark.parametrize("mach", [0.3, 1.5])
+def test_floor_rule_is_inert_in_fp64(orc, tol, mach):
+    """The round-off floor stop (taken where a full Newton step no longer
+    lowers the residual while it is within 8 times the bound) exists for the
+    FP32 arithmetic of the reduced-precision kernels, whose residual floor
+    (1e-7..1e-6) lies close to their 1e-5 stop; both sides carry it so that
+    they implement one algorithm.  In FP64 at the tolerances used here
+    (1e-12 and the tighter 1e-14) the floor lies 100-1000 times below the
+    bound and the rule never fires: trajectories with it on and off are
+    bitwise identical, on subsonic and supersonic states alike."""
+    shape = (12, 6, 6)
+    n = 12 * 6 * 6
+    T0 = 2.0 / 3.0 if mach > 1 else 0.5
+    U = mach * np.sqrt(1.4 * T0)
+    rng = np.random.default_rng(31)
+    rho = 1 + 0.05 * rng.standard_normal(n)
+    u = np.zeros((3, n))
+    u[0] = U * (1 + 0.05 * rng.standard_normal(n))
+    u[1] = 0.1 * U * rng.standard_normal(n)
+    T = T0 * (1 + 0.05 * rng.standard_normal(n))
+    out = []
+    for rule in (True, False):
+        o = orc.Oracle(*shape, gamma=1.4, tau=0.55, newton_tol=tol, newton_maxit=30, floor_rule=rule)
+        assert o.init(rho, u.reshape(-1), T) == 0
+        o.step(4)
+        assert o.stats.failed == 0 and o.stats.iterations > 0
+        out.append((o.f.copy(), o.g.copy(), o.lam.copy(), o.stats.evaluations))
+    for a, b in zip(out[0][:3], out[1][:3]):
+        np.testing.assert_array_equal(a, b)
+    assert out[0][3] == out[1][3]
+
+
+def test_failed_cells_are_marked_and_not_restarted_cold(orc):
+    """Bounded cost of cells without an equilibrium (reading): a cell that
+    failed is marked by a NaN lambda_0 (lambda_1..12 kept); in the next step
+    it warm-starts from its other multipliers (lambda_0 normalising) and is
+    not restarted cold, so a persistently failing cell costs at most one
+    capped Newton attempt per step (maxit updates of at most 40 f^eq
+    evaluations each).  A marked cell whose moments do have an equilibrium
+    converges to it as an unmarked one does."""
+    shape = (8, 4, 4)
+    n = int(np.prod(shape))
+    rho, u, T = inputs.uniform_fields(n, 1.0, [0.1, 0.0, 0.0], 0.5)
+    o = orc.Oracle(*shape, gamma=1.4, tau=0.6, newton_tol=1e-13, newton_maxit=20)
+    o.init(rho, u, T)
+    f, g, lam = o.f.copy(), o.g.copy(), o.lam.copy()
+    # every cell cold (T = 0.1 at u = 0.1 has no 13-moment equilibrium), through g
+    c = orc.velocities()
+    q = (c ** 2).sum(1)
+    F = f.reshape(39, n)
+    e_now = (F * q[:, None]).sum(0) + g.reshape(39, n).sum(0)
+    G = g.reshape(39, n) + ((1.0 * 0.01 + 5.0 * 0.1 - e_now) / 39.0)[None, :]
+    runs = {}
+    for skip in (True, False):
+        s = orc.Oracle(*shape, gamma=1.4, tau=0.6, newton_tol=1e-13, newton_maxit=20,
+                       skip_cold_after_failure=skip)
+        s.set_state(f, G.reshape(-1), lam)
+        s.step(1)
+        assert s.stats.failed == n and s.stats.cold_restarts == n
+        assert np.isnan(s.lam.reshape(13, n)[0]).all()
+        np.testing.assert_array_equal(s.lam.reshape(13, n)[1:], lam.reshape(13, n)[1:])
+        ev1 = s.stats.evaluations
+        s.step(1)
+        runs[skip] = (s.stats.failed, s.stats.cold_restarts, s.stats.evaluations, ev1)
+    failed, cold, ev2, ev1 = runs[True]
+    assert failed == n and cold == 0
+    assert ev2 <= n * (1 + 20 * 40) and ev2 < ev1
+    assert runs[False][1] == n and runs[False][2] > ev2
+    # marked cells with a realizable state: same result as unmarked ones
+    lam_marked = lam.copy().reshape(13, n)
+    lam_marked[0, ::3] = np.nan
+    pert = inputs.random_perturbation(shape, seed=41, amplitudes=(0.02,))
+    fp, gp = f * np.exp(pert[0].reshape(-1)), g * np.exp(pert[1].reshape(-1))
+    a = orc.Oracle(*shape, gamma=1.4, tau=0.6, newton_tol=1e-13)
+    b = orc.Oracle(*shape, gamma=1.4, tau=0.6, newton_tol=1e-13)
+    a.set_state(fp, gp, lam)
+    b.set_state(fp, gp, lam_marked.reshape(-1))
+    a.step(1)
+    b.step(1)
+    assert a.stats.failed == 0 and b.stats.failed == 0 and b.stats.cold_restarts == 0
+    assert not np.isnan(b.lam).any()
+    assert np.max(np.abs(a.f - b.f)) <= 1e-12 * np.abs(a.f).max()
+    assert np.max(np.abs(a.g - b.g)) <= 1e-12 * np.abs(a.g).max()
