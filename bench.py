@@ -90,6 +90,52 @@ def run_mode(mode, n, steps, warmup):
     }
 
 
+def run_case(case, mode, develop, steps):
+    """One obstacle workload of the method at its full size (the supersonic
+    airfoil of Sec. 4, 2048 x 1024 x 1, or the sphere in a 512 x 256 x 256
+    channel) in one storage mode: `develop` untimed steps from the free
+    stream, so that the shocks and the wake have formed, then `steps` timed
+    ones.  Algorithmic bytes per cell add the 8-byte link mask that an
+    obstacle's cells read."""
+    import numpy as np
+    import torch
+
+    from paper_1910_13515_amd import lbm, precision_study
+    make = {"airfoil": precision_study.airfoil_case, "sphere": precision_study.sphere_case}[case]
+    shape, solid, kw = make(1.0)
+    s = lbm.Solver(shape, solid=solid, storage=mode, **kw)
+    cells = int(np.prod(shape))
+    done = 0
+    while done < develop:
+        k = min(500, develop - done)
+        s.step(k)
+        done += k
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(s.stream)
+    s.step(steps)
+    end.record(s.stream)
+    end.synchronize()
+    ms = start.elapsed_time(end)
+    st = s.step(1, stats=True)
+    info = s.info()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    ms_step = ms / steps
+    bpc = BYTES_PER_CELL[mode] + 8
+    achieved = bpc * cells / (ms_step * 1e-3) / 1e9
+    return {"workload": f"{case} {'x'.join(map(str, shape))}, Ma {kw['mach']}, Re {kw['reynolds']:g}, "
+                        f"T_ref {kw['T_ref']:.4g}, {mode}, timed after {develop} steps",
+            "glups": cells * steps / (ms * 1e-3) / 1e9, "ms_per_step": ms_step, "steps": steps, "tau": info.tau,
+            "newton_iterations_per_cell": st.iterations / max(1, st.cell_updates),
+            "failed_cells_next_step": int(st.failed), "alpha_hist": list(st.alpha_hist),
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_cell": bpc,
+                         "cells_per_launch": cells}}
+
+
 # device sources, and the host layer that sets their run-time parameters
 # (default Newton tolerances change the instruction counts)
 KERNEL_SOURCES = ["lbm_kernels.hip", "equilibrium.h", "d3q39.h", "slot.h", "lbm_api.cpp"]
@@ -314,8 +360,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=40)
-    ap.add_argument("--serving-rate", type=float, default=3.0)
+    # 0.8 of the pool's capacity on this mix: about 3.6 GLUPS over a mean of
+    # 1.65e9 cell updates per request is 2.2 requests/s
+    ap.add_argument("--serving-rate", type=float, default=1.75)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the obstacle workloads (FP32 airfoil, FP16 sphere, each beside FP64)")
     ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--serving-side", default="both", choices=["both", "batched", "sequential"],
                     help="with --serving-only: run one side of the comparison alone (for profiling)")
@@ -359,6 +409,17 @@ def main():
             r = run_mode(m, args.n, args.steps, args.warmup)
             print(f"# {m}: {r['glups']:.3f} GLUPS, {r['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
             modes[m] = r
+    configs = {}
+    if not args.no_configs:
+        # the airfoil compares FP32-shifted storage with FP64, the sphere
+        # FP16-shifted with FP32 and FP64 (each at its full size)
+        for case, modes_c, develop, steps_c in (("airfoil", ("fp32s", "fp64"), 2000, 200),
+                                                ("sphere", ("fp16s", "fp32s", "fp64"), 200, 20)):
+            for m in modes_c:
+                r = run_case(case, m, develop, steps_c)
+                print(f"# {case} {m}: {r['glups']:.3f} GLUPS, {r['ms_per_step']:.3f} ms/step", file=sys.stderr,
+                      flush=True)
+                configs[f"{case}_{m}"] = r
     serving = None if args.no_serving else serving_leg(args.serving_requests, args.serving_rate)
     cpu = None if args.no_cpu else cpu_baseline()
     roof = dict(main_res["roofline"])
@@ -399,6 +460,7 @@ def main():
         "alu": with_ceiling(roof, measured_alu(args.mode, main_res["ms_per_step"])),
         "cpu_baseline": cpu,
         "modes": modes,
+        "configs": configs,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)

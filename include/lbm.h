@@ -55,14 +55,16 @@ typedef enum {
 } lbm_status;
 
 /* The shifted modes stop Newton at 1e-5 of the largest target (FP32
- * arithmetic) and then remove the five collision-invariant residuals with a
- * correction proportional to the rest-state weights, so that mass, momentum
- * and energy are conserved.  Far from rest (a supersonic stream) that
- * correction is large against the smallest equilibrium populations, and the
- * Knudsen sensor of Eq. (eq:DeltaAvg) reads high there: more cells take the
- * stronger relaxation branches of Eq. (eq:alpha) than in FP64.  The moments
- * stay within the FP64 run's own round-off sensitivity on the supersonic
- * airfoil and sphere flows. */
+ * arithmetic) and then remove the five collision-invariant residuals that
+ * stop leaves (mass, momentum, energy) by scaling each equilibrium
+ * population by 1 + x . (1, xi_i, |xi_i|^2), with x solving the 5x5 system of
+ * the equilibrium's own moments.  The correction is proportional to each
+ * population, so the smallest equilibria of a supersonic stream (1e-11 and
+ * below) keep their relative accuracy and the Knudsen sensor of
+ * Eq. (eq:DeltaAvg) stays at the FP64 value within the arithmetic's bound.
+ * Storage as deviations from the rest weights rounds the smallest
+ * populations of a fast stream to the spacing of their (much larger)
+ * weights; shift_ref = 1 stores them near exactly. */
 typedef enum {
     LBM_STORE_FP64 = 0,          /* populations and multipliers in FP64, arithmetic in FP64 */
     LBM_STORE_FP32_SHIFTED = 1,  /* populations stored in FP32 as deviations from shift weights, FP32 arithmetic */
@@ -85,7 +87,8 @@ typedef struct {
                                   opposite velocities have unequal weights, and a bounce-back moves the
                                   gathered deviation onto the other weight (FP16: one more rounding) */
     int32_t kn_relax;          /* 1: tau(eps) = tau * alpha(eps), Eq. (eq:alpha); 0: plain BGK */
-    int32_t newton_maxit;      /* cap on Newton updates per cell and step (0: 20) */
+    int32_t newton_maxit;      /* cap on Newton updates per cell and step (0: 20); a cold restart, where
+                                  allowed, has a cap of max(newton_maxit, 100) */
     int32_t faces[6];          /* lbm_face for -x, +x, -y, +y, -z, +z */
     double gamma;              /* heat-capacity ratio, 1 < gamma <= 5/3 (C_v = 1/(gamma-1), D = 3) */
     double mach;               /* |u_ref| / sqrt(gamma T_ref) */
@@ -95,7 +98,11 @@ typedef struct {
     double u_dir[3];           /* direction of u_ref (normalised here; zero vector with mach = 0 is allowed) */
     double tau;                /* > 0: relaxation time as given; <= 0: derived from reynolds */
     double newton_tol;         /* stopping bound on max_k |G_k|/rho relative to max(1, max_k |M_k|/rho)
-                                  (0: 1e-12 in FP64 as in Sec. 5, 1e-5 in FP32 arithmetic) */
+                                  (0: 1e-12 in FP64 as in Sec. 5, 1e-5 in FP32 arithmetic).  A solve also
+                                  stops at the arithmetic's round-off floor: when the full Newton step does
+                                  not lower ||G||_2 while max_k |G_k| before and after it is within 8 times
+                                  the bound, the step is taken (this fires in FP32 arithmetic; in FP64 the
+                                  floor lies far below the bound) */
     const uint8_t *solid;      /* nx*ny*nz obstacle flags (nonzero = solid) or NULL */
     const double *init_rho;    /* initial fields (N, 3N as ux|uy|uz, N) or NULL for the reference state */
     const double *init_u;
@@ -108,7 +115,7 @@ typedef struct {
     int64_t iterations;        /* accepted Newton updates */
     int64_t max_iterations;    /* largest count of one cell in one step */
     int64_t failed;            /* cell-steps whose Newton did not converge */
-    int64_t cold_restarts;     /* cell-steps whose warm start failed and were restarted cold */
+    int64_t cold_restarts;     /* cell-steps whose warm start failed and that were restarted cold */
     int64_t alpha_hist[4];     /* cell-steps per branch of Eq. (eq:alpha) */
     int64_t wave_iterations;   /* sum over wave-steps of the largest count in the wave (64 cells) */
     int64_t waves;             /* wave-steps (a wave runs as many Newton updates as its slowest cell) */
@@ -133,14 +140,23 @@ int32_t lbm_version(void);
 int lbm_velocities(int32_t *out);
 
 /* Bytes of device arena that lbm_create() needs for these parameters, or a
- * negative lbm_status if they are invalid.  This is the admission footprint. */
+ * negative lbm_status if they are invalid.  This is the admission footprint:
+ * two ping-pong buffers of the 2 x 39 populations per cell (f and g of
+ * Sec. 3, Eq. (eq:discrete-equilibrium-poly)), the 13 multipliers per cell
+ * that warm-start the next solve (Sec. 5 algorithm table), the obstacle's
+ * link masks and the reduction scratch. */
 int64_t lbm_required_bytes(const lbm_params *params);
 
-/* Validates the parameters, sub-allocates the arena (device pointer, 256-byte
- * aligned, at least lbm_required_bytes()), uploads the obstacle and initial
- * fields and writes the initial state: every cell at the equilibrium of its
- * initial (rho, u, T), multipliers from a cold-started Newton solve.  Blocks
- * until the initial state is written.  On success *out owns the context; on
+/* The problem of Sec. 4: a polyatomic gas of ratio gamma (Sec. 2, C_v =
+ * 1/(gamma-1), g^eq of Eq. (eq:discrete-equilibrium-poly)) at Mach and
+ * Reynolds numbers, with an obstacle under half-way bounce-back and
+ * free-stream equilibrium or Neumann faces.  Validates the parameters,
+ * sub-allocates the arena (device pointer, 256-byte aligned, at least
+ * lbm_required_bytes()), uploads the obstacle and initial fields and writes
+ * the initial state: every cell at the equilibrium of its initial (rho, u, T)
+ * (Eq. (eq:discrete-equilibrium) with the targets of Eq. (eq:13constraints)),
+ * multipliers from a cold-started Newton solve.  Blocks until the initial
+ * state is written.  On success *out owns the context; on
  * failure *out is NULL, no host memory is kept and lbm_last_error(NULL) holds
  * the message. */
 int lbm_create(const lbm_params *params, void *dev_arena, int64_t arena_bytes, void *hip_stream, lbm_ctx **out);
@@ -150,11 +166,19 @@ int lbm_create(const lbm_params *params, void *dev_arena, int64_t arena_bytes, v
  * fills *stats.  A fluid cell whose 13 multipliers are not found (warm start,
  * then cold start) is not collided in that step: its gathered populations are
  * stored unchanged and its multipliers kept, so every moment of the cell is
- * conserved.  With stats, returns LBM_E_NEWTON when that happened (the number
+ * conserved; multiplier 0 is replaced by NaN as the mark of that failure.  In
+ * its next step a marked cell starts from its other 12 multipliers (lambda_0
+ * normalising) and is not restarted cold, which bounds the cost of a cell
+ * without equilibrium to one capped attempt per step.  A Newton attempt also
+ * ends when its line search finds no step length (down to 2^-39) that lowers
+ * ||G||_2.  With stats, returns LBM_E_NEWTON when a cell failed (the number
  * of such cell updates is stats->failed); the state stays defined. */
 int lbm_step(lbm_ctx *ctx, int32_t nsteps, lbm_step_stats *stats);
 
-/* Macroscopic fields of the current state, in FP64.  out_host (nullable):
+/* Macroscopic fields of the current state, in FP64: rho, u and T of the
+ * populations (Sec. 3; T from the total energy sum_i f_i |xi_i|^2 + g_i with
+ * E = |u|^2/2 + C_v T, Sec. 2).  Collision conserves them, so after n steps
+ * they are those of the stored post-collision state.  out_host (nullable):
  * 5*N doubles, SoA rho | ux | uy | uz | T; NaN at solid cells; Neumann
  * boundary cells report the interior cell they copy.  totals (nullable):
  * mass, momentum x, y, z and total energy (sum over i of (f_i |xi_i|^2 +
@@ -167,13 +191,16 @@ int lbm_moments(lbm_ctx *ctx, double *out_host, double *totals);
  * Sec. 4 shows for the airfoil (Fig. fig:naca-knudsen), and the number of
  * Newton iterations the cell's solve takes (warm start; the cold restart's
  * count when that is used).  eps_out (nullable): N doubles, NaN outside fluid
- * cells and where the solve fails; iters_out (nullable): N int32, -1 outside
+ * cells and where the solve fails, +inf where an equilibrium population
+ * underflows in the arithmetic (branch alpha = 1/tau of Eq. (eq:alpha));
+ * iters_out (nullable): N int32, -1 outside
  * fluid cells, the iteration cap where the solve fails.  Uses the moments
  * scratch of the arena.  Synchronises. */
 int lbm_diagnostics(lbm_ctx *ctx, double *eps_out, int32_t *iters_out);
 
 /* Copies the state to host FP64 arrays (each nullable): f and g as [39][N],
- * multipliers as [13][N].  Shifted storage is decoded.  Synchronises. */
+ * multipliers as [13][N] (multiplier 0 is NaN for a cell whose last solve
+ * failed, see lbm_step).  Shifted storage is decoded.  Synchronises. */
 int lbm_get_state(lbm_ctx *ctx, double *f, double *g, double *lam);
 
 /* Replaces the state (all three arrays required, layouts as above; shifted

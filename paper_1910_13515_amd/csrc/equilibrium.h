@@ -13,8 +13,37 @@ namespace lbm13 {
 
 template <class C>
 __device__ __forceinline__ C dexp(C x);
+
+// exp in FP64 by Cody and Waite's argument reduction, x = k ln2 + r with
+// |r| <= ln2 / 2 (ln2 split into a 32-bit head, exact in k * head, and a
+// tail), and the Taylor polynomial of e^r to degree 12 (truncation below
+// 2e-16 relative), scaled by 2^k.  Non-finite or out-of-range arguments give
+// non-finite or zero results through the scaling, which the solver treats
+// as a failed evaluation.
 template <>
-__device__ __forceinline__ double dexp<double>(double x) { return exp(x); }
+__device__ __forceinline__ double dexp<double>(double x)
+{
+    constexpr double kLog2e = 0x1.71547652b82fep+0;
+    constexpr double kLn2Hi = 0x1.62e42fee00000p-1;
+    constexpr double kLn2Lo = 0x1.a39ef35793c76p-33;
+    const double k = __builtin_rint(x * kLog2e);
+    double r = __builtin_fma(-k, kLn2Hi, x);
+    r = __builtin_fma(-k, kLn2Lo, r);
+    double p = 1.0 / 479001600.0;  // 1/12!
+    p = __builtin_fma(p, r, 1.0 / 39916800.0);
+    p = __builtin_fma(p, r, 1.0 / 3628800.0);
+    p = __builtin_fma(p, r, 1.0 / 362880.0);
+    p = __builtin_fma(p, r, 1.0 / 40320.0);
+    p = __builtin_fma(p, r, 1.0 / 5040.0);
+    p = __builtin_fma(p, r, 1.0 / 720.0);
+    p = __builtin_fma(p, r, 1.0 / 120.0);
+    p = __builtin_fma(p, r, 1.0 / 24.0);
+    p = __builtin_fma(p, r, 1.0 / 6.0);
+    p = __builtin_fma(p, r, 0.5);
+    p = __builtin_fma(p, r, 1.0);
+    p = __builtin_fma(p, r, 1.0);
+    return __builtin_ldexp(p, (int)k);
+}
 template <>
 __device__ __forceinline__ float dexp<float>(float x) { return __expf(x); }  // v_exp_f32 on x log2(e)
 
@@ -190,9 +219,10 @@ __device__ __forceinline__ bool cholesky_solve(C (&J)[kM][kM], const C G[kM], C 
 }
 
 // Multipliers of the Maxwellian shape (cold start): lam_1 = u/T,
-// lam_2 = -delta/(2T), lam_3 = 0, lam_0 normalising sum_i exp(...) to 1.
+// lam_2 = -delta/(2T), lam_3 = 0; lam_0 is set by the solver so that the
+// exponentials sum to 1.
 template <class C>
-__device__ __forceinline__ void cold_guess(const C u[3], C T, C lam[kM])
+__device__ __forceinline__ void maxwellian_shape(const C u[3], C T, C lam[kM])
 {
 #pragma unroll
     for (int k = 0; k < kM; ++k) lam[k] = C(0);
@@ -200,25 +230,46 @@ __device__ __forceinline__ void cold_guess(const C u[3], C T, C lam[kM])
     lam[2] = u[1] / T;
     lam[3] = u[2] / T;
     lam[4] = lam[5] = lam[6] = C(-0.5) / T;
+}
+
+// lam_0 = -log of the sum of the exponentials at lam_0 = 0, so that the
+// exponentials sum to 1
+template <class C>
+__device__ __forceinline__ void normalise_lam0(C lam[kM])
+{
+    lam[0] = C(0);
     C f0, fp[kPairs], fm[kPairs];
     eval_exponentials(lam, f0, fp, fm);
-    C s = f0;
+    C sum = f0;
 #pragma unroll
-    for (int p = 0; p < kPairs; ++p) s += fp[p] + fm[p];
-    lam[0] = -dlog(s);
+    for (int p = 0; p < kPairs; ++p) sum += fp[p] + fm[p];
+    lam[0] = -dlog(sum);
 }
+
+// how solve_multipliers starts
+enum SolveStart : int {
+    kStartWarm = 0,    // from lam; one cold restart if that fails
+    kStartMarked = 1,  // from lam_1..12 of a cell that failed the previous step (lam_0 not valid); no cold restart
+    kStartCold = 2,    // from the Maxwellian shape only
+};
 
 // Newton-Raphson for the multipliers, warm-started from lam.  Stopping rule:
 // max_k |G_k| <= tol * max(1, max_k |m_k|).  Step halving while the Euclidean
-// norm of G does not decrease (at most 39 halvings, then the step is taken).
-// If the warm start fails (cap reached, J not positive definite, or a value
-// not finite) the solve restarts once from the Maxwellian shape with cap
-// maxit_cold.  On return lam, f0, fp, fm hold the last accepted iterate and
-// iters the number of accepted updates of the final attempt (maxit if both
-// attempts failed).  The targets m are evaluated from (u, T) where needed.
+// norm of G does not decrease, trying t = 1, 1/2, ..., 2^-39; when no trial
+// lowers it the attempt has stalled and fails (no descent is left, which is
+// what happens where no multipliers satisfy the constraints).  If the warm
+// start fails (cap reached, stall, J not positive definite, or a value not
+// finite) the solve restarts once from the Maxwellian shape with cap
+// maxit_cold (start = kStartWarm only).  Where lam_0 is to be set (kStartMarked
+// and every cold start) it is -log of the sum of the exponentials at
+// lam_0 = 0, so that the start sums to 1.  On return lam, f0, fp, fm
+// hold the last accepted iterate, G its residual (all zero after a failure),
+// and iters the number of accepted updates of the final attempt (maxit if the
+// solve failed).  The targets m are evaluated from (u, T) where needed.
 template <class C>
 __device__ __forceinline__ int solve_multipliers(const C u[3], C T, C lam[kM], C &f0, C fp[kPairs], C fm[kPairs],
-                                                 C tol, int maxit, int maxit_cold, int &iters, C (&resid)[5])
+                                                 C tol, int maxit, int maxit_cold, int start, int &iters,
+                                                 C (&G)[kM])
 {
     C m[kM];
     mb_targets(u, T, m);
@@ -235,10 +286,14 @@ __device__ __forceinline__ int solve_multipliers(const C u[3], C T, C lam[kM], C
     for (int k = 0; k < kM; ++k) d[k] = C(0);
     C t = C(0);
     C n0 = C(0);
-    int it = 0, ls = 0, cap = maxit;
-    bool fresh = true, cold = false, floor_stop = false;
+    const bool from_cold = start == kStartCold;
+    int it = 0, ls = 0, cap = from_cold ? maxit_cold : maxit;
+    bool fresh = true, cold = start != kStartWarm, floor_stop = false;
+    bool restarted = from_cold;  // the current attempt started from the Maxwellian shape
     bool near = false;  // the last accepted iterate is within 8 times the bound
     int status = kFailed;
+    if (from_cold) maxwellian_shape(u, T, lam);
+    if (start != kStartWarm) normalise_lam0(lam);
     for (;;) {
         eval_exponentials(lam, f0, fp, fm);
         C s[kPairs], a[kPairs];
@@ -247,7 +302,6 @@ __device__ __forceinline__ int solve_multipliers(const C u[3], C T, C lam[kM], C
             s[p] = fp[p] + fm[p];
             a[p] = fp[p] - fm[p];
         }
-        C G[kM];
         residual_impl(f0, s, a, u, T, h, G, BasisSeq{});
         C n2 = C(0);
 #pragma unroll
@@ -263,28 +317,25 @@ __device__ __forceinline__ int solve_multipliers(const C u[3], C T, C lam[kM], C
         // and the step's end are both within 8 times the bound: the residual
         // sits at the round-off floor; the step is taken and the solve stops
         floor_stop = !fresh && !(n2 < n0) && ls == 0 && near && r <= C(8) * bound;
-        if (!fresh && !(n2 < n0) && ls < 39 && !floor_stop) {
+        const bool rejected = !fresh && !(n2 < n0) && !floor_stop;
+        if (rejected && ls < 39) {
             t *= C(0.5);
             ++ls;
 #pragma unroll
             for (int k = 0; k < kM; ++k) lam[k] += t * d[k];
             continue;
         }
-        if (!fresh) ++it;
-        fresh = false;
-        // residuals of the collision invariants at the accepted iterate:
-        // mass, momentum, and sum_i f_i |xi_i|^2 (trace of the second moment)
-        resid[0] = G[0];
-        resid[1] = G[1];
-        resid[2] = G[2];
-        resid[3] = G[3];
-        resid[4] = G[4] + G[5] + G[6];
-        near = r <= C(8) * bound;
-        if (r <= bound || floor_stop) {
-            status = cold ? kConvergedCold : kConverged;
-            break;
+        bool bad = rejected;  // no trial lowered the residual: stalled
+        if (!bad) {
+            if (!fresh) ++it;
+            fresh = false;
+            near = r <= C(8) * bound;
+            if (r <= bound || floor_stop) {
+                status = restarted ? kConvergedCold : kConverged;
+                break;
+            }
+            bad = !(r - r == C(0)) || it >= cap;  // not finite, or cap reached
         }
-        bool bad = !(r - r == C(0)) || it >= cap;  // not finite, or cap reached
         if (!bad) {
             C J[kM][kM];
             jacobian_impl(f0, s, a, J, BasisSeq{});
@@ -296,7 +347,9 @@ __device__ __forceinline__ int solve_multipliers(const C u[3], C T, C lam[kM], C
                 break;
             }
             cold = true;
-            cold_guess(u, T, lam);
+            restarted = true;
+            maxwellian_shape(u, T, lam);
+            normalise_lam0(lam);
             it = 0;
             ls = 0;
             cap = maxit_cold;
@@ -317,43 +370,100 @@ __device__ __forceinline__ int solve_multipliers(const C u[3], C T, C lam[kM], C
 #pragma unroll
         for (int p = 0; p < kPairs; ++p) fp[p] = fm[p] = C(0);
 #pragma unroll
-        for (int k = 0; k < 5; ++k) resid[k] = C(0);
+        for (int k = 0; k < kM; ++k) G[k] = C(0);
     }
     iters = status == kFailed ? maxit : it;
     return status;
 }
 
-// Remove the residual of the collision invariants from an equilibrium (per
-// unit density) that satisfies the constraints only to a tolerance:
-// f_i += w_i (a + b . xi_i + c |xi_i|^2) with the isotropic rest weights w
-// of each shell, so that sum_i f_i (1, xi_i, |xi_i|^2) is exact.  With
-// isotropic weights the five equations decouple: b_a = -R_a / W2 and (a, c)
-// from the 2x2 system [[W0, Wq], [Wq, Wqq]] (a, c) = -(R_0, R_E), whose
-// inverse is passed in (inv = {i00, i01, i11}).
-template <int P, class C>
-__device__ __forceinline__ void project_pair(C *fp, C *fm, C a, C c, const C b[3], const float *wshell)
+// Remove the residuals of the five collision invariants, R = sum_i f_i psi_i
+// - target with psi = (1, xi, |xi|^2), that a solve stopped at a tolerance
+// leaves in the equilibrium f (per unit density):
+//     f_i <- f_i (1 + x . psi_i),   M x = -R,   M = sum_i f_i psi_i psi_i^T,
+// after which sum_i f_i psi_i equals the targets exactly in exact
+// arithmetic.  The correction of each population is proportional to the
+// population itself, so it keeps every population's relative change at the
+// level of the residuals, however small the population.  The entries of M
+// are moments of f: the constrained ones are target + residual (the residual
+// G of the accepted iterate), and sum_i f_i |xi_i|^4 is summed here.  M is a
+// Gram matrix of 5 independent functions with positive weights, hence SPD;
+// its Cholesky factor gives x.  ok = false (no equilibrium) leaves f alone.
+template <class C>
+__device__ __forceinline__ void project_invariants(C &f0, C *fp, C *fm, const C u[3], C T, const C (&G)[kM],
+                                                   bool ok)
 {
-    constexpr int cx = kPairVel[P][0], cy = kPairVel[P][1], cz = kPairVel[P][2];
-    const C w = C(wshell[shell_of_q(pair_q(P))]);
-    const C even = w * (a + C(pair_q(P)) * c);
-    C odd = C(-0.0);
-    odd = Term<cx>::add(odd, b[0]);
-    odd = Term<cy>::add(odd, b[1]);
-    odd = Term<cz>::add(odd, b[2]);
-    odd *= w;
-    fp[P] += even + odd;
-    fm[P] += even - odd;
-}
-
-template <class C, int... P>
-__device__ __forceinline__ void project_invariants(C &f0, C *fp, C *fm, const C (&resid)[5], const float *wshell,
-                                                   const float *inv, float inv_w2, std::integer_sequence<int, P...>)
-{
-    const C a = -(C(inv[0]) * resid[0] + C(inv[1]) * resid[4]);
-    const C c = -(C(inv[1]) * resid[0] + C(inv[2]) * resid[4]);
-    const C b[3] = {-resid[1] * C(inv_w2), -resid[2] * C(inv_w2), -resid[3] * C(inv_w2)};
-    f0 += C(wshell[0]) * a;
-    (project_pair<P, C>(fp, fm, a, c, b, wshell), ...);
+    C q4 = C(-0.0);
+    [&]<int... P>(std::integer_sequence<int, P...>) {
+        ((q4 = Term<pair_q(P) * pair_q(P)>::add(q4, fp[P] + fm[P])), ...);
+    }(PairSeq{});
+    const C uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const C h = uu + C(5) * T;
+    // M in the order (1, xi_x, xi_y, xi_z, |xi|^2); lower triangle
+    C M[5][5];
+    M[0][0] = C(1) + G[0];
+    M[1][0] = u[0] + G[1];
+    M[2][0] = u[1] + G[2];
+    M[3][0] = u[2] + G[3];
+    M[4][0] = (uu + C(3) * T) + ((G[4] + G[5]) + G[6]);
+    M[1][1] = u[0] * u[0] + T + G[4];
+    M[2][2] = u[1] * u[1] + T + G[5];
+    M[3][3] = u[2] * u[2] + T + G[6];
+    M[2][1] = u[0] * u[1] + G[7];
+    M[3][1] = u[0] * u[2] + G[8];
+    M[3][2] = u[1] * u[2] + G[9];
+    M[4][1] = h * u[0] + G[10];
+    M[4][2] = h * u[1] + G[11];
+    M[4][3] = h * u[2] + G[12];
+    M[4][4] = q4;
+    const C R[5] = {G[0], G[1], G[2], G[3], (G[4] + G[5]) + G[6]};
+    // Cholesky M = L L^T in place (L scaled by the reciprocal pivots)
+    C rd[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        C sj = M[j][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) sj -= M[j][k] * M[j][k];
+        rd[j] = rsqrt_(sj);
+#pragma unroll
+        for (int i = j + 1; i < 5; ++i) {
+            C tij = M[i][j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) tij -= M[i][k] * M[j][k];
+            M[i][j] = tij * rd[j];
+        }
+    }
+    C y[5], x[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        C ti = -R[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) ti -= M[i][k] * y[k];
+        y[i] = ti * rd[i];
+    }
+#pragma unroll
+    for (int i = 4; i >= 0; --i) {
+        C ti = y[i];
+#pragma unroll
+        for (int k = i + 1; k < 5; ++k) ti -= M[k][i] * x[k];
+        x[i] = ti * rd[i];
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) x[k] = ok ? x[k] : C(0);
+    f0 += f0 * x[0];
+    [&]<int... P>(std::integer_sequence<int, P...>) {
+        (
+            [&] {
+                constexpr int cx = kPairVel[P][0], cy = kPairVel[P][1], cz = kPairVel[P][2];
+                const C even = Term<pair_q(P)>::add(x[0], x[4]);
+                C odd = C(-0.0);
+                odd = Term<cx>::add(odd, x[1]);
+                odd = Term<cy>::add(odd, x[2]);
+                odd = Term<cz>::add(odd, x[3]);
+                fp[P] += fp[P] * (even + odd);
+                fm[P] += fm[P] * (even - odd);
+            }(),
+            ...);
+    }(PairSeq{});
 }
 
 // equilibrium per unit density of velocity i from the solve's exponentials

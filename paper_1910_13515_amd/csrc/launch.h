@@ -20,6 +20,7 @@ hipError_t launch_single_equilibrium(double rho, const double u[3], double T, do
 hipError_t launch_moments(int storage, const SlotDesc &d, int parity, double *out, double *partial, double *totals,
                           hipStream_t st);
 int moments_partial_blocks(int64_t n);
+
 hipError_t launch_zero(int64_t *p, int64_t count, hipStream_t st);
 hipError_t launch_reduce_stats(const int64_t *partial, int nwaves, int64_t *out, hipStream_t st);
 hipError_t launch_decode_pop(int storage, const SlotDesc &d, int parity, int pop, double *out, hipStream_t st);

@@ -367,25 +367,6 @@ int create_in(lbm_ctx *c, const lbm_params *params)
         d.ref_energy = (float)ener;
     }
 
-    // projection constants for FP32 arithmetic (rest weights per shell)
-    {
-        double W0 = 0, Wq = 0, Wqq = 0, W2 = 0;
-        for (int i = 0; i < kQ; ++i) {
-            const int cx = vel(i, 0), cy = vel(i, 1), cz = vel(i, 2);
-            const double q = cx * cx + cy * cy + cz * cz;
-            d.proj_w[shell(i)] = (float)rest[i];
-            W0 += rest[i];
-            Wq += rest[i] * q;
-            Wqq += rest[i] * q * q;
-            W2 += rest[i] * cx * cx;
-        }
-        const double det = W0 * Wqq - Wq * Wq;
-        d.proj_inv[0] = (float)(Wqq / det);
-        d.proj_inv[1] = (float)(-Wq / det);
-        d.proj_inv[2] = (float)(W0 / det);
-        d.proj_inv_w2 = (float)(1.0 / W2);
-    }
-
     // obstacle links
     const int64_t n = d.n;
     if (params->solid) {

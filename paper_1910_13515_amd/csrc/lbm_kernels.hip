@@ -306,19 +306,24 @@ __device__ __forceinline__ void diag_cell(const SlotDesc &d, const S *src, int x
 
     C f0, fp[kPairs], fm[kPairs];
     int iters = 0;
-    C resid[5];
-    const int status = solve_multipliers<C>(u, T, lam, f0, fp, fm, C(d.tol), d.maxit, d.maxit_cold, iters, resid);
+    C G[kM];
+    // a NaN lambda_0 marks a cell that had no equilibrium in the previous step
+    const bool marked = !(lam[0] == lam[0]);
+    const int status = solve_multipliers<C>(u, T, lam, f0, fp, fm, C(d.tol), d.maxit, d.maxit_cold,
+                                            marked ? kStartMarked : kStartWarm, iters, G);
     if constexpr (sizeof(C) == 4) {
         // FP32 arithmetic stops at a tolerance far above FP64's; make the
         // collision invariants exact so that the bias of the last Newton
         // step (its mass and energy residuals are positive) does not
         // accumulate over time steps
-        project_invariants(f0, fp, fm, resid, d.proj_w, d.proj_inv, d.proj_inv_w2, PairSeq{});
+        project_invariants(f0, fp, fm, u, T, G, status != kFailed);
     }
 
     // Knudsen sensor over f (Eq. eq:DeltaAvg)
     const C eps = eps_sum<S, C>(d, rho, f0, fp, fm, pk, VelSeq{}) * C(1.0 / kQ);
-    diag[cell] = status == kFailed ? __builtin_nan("") : (double)eps;
+    // an equilibrium population that underflows makes its term, and eps,
+    // infinite (0 * inf gives NaN where the gathered value underflows too)
+    diag[cell] = status == kFailed ? __builtin_nan("") : (eps == eps ? (double)eps : __builtin_inf());
     diag[d.n + cell] = (double)iters;
 }
 
@@ -523,9 +528,22 @@ __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const 
 
     C f0, fp[kPairs], fm[kPairs];
     int iters = 0;
-    C resid[5];
-    const int status = solve_multipliers<C>(u, T, lam, f0, fp, fm, C(d.tol), d.maxit, d.maxit_cold, iters, resid);
-    project_invariants(f0, fp, fm, resid, d.proj_w, d.proj_inv, d.proj_inv_w2, PairSeq{});
+    C G[kM];
+    // a NaN lambda_0 marks a cell that had no equilibrium in the previous
+    // step: its warm start normalises the other multipliers and it is not
+    // restarted cold
+    const bool marked = !(lam[0] == lam[0]);
+    const int status = solve_multipliers<C>(u, T, lam, f0, fp, fm, C(d.tol), d.maxit, d.maxit_cold,
+                                            marked ? kStartMarked : kStartWarm, iters, G);
+    const bool failed = status == kFailed;
+    // the multipliers leave first (their registers are free for what follows)
+    if (!failed) {
+#pragma unroll
+        for (int k = 0; k < kM; ++k) gstore<C>(lamb + (uint64_t)k * nS64, cellS, lam[k]);
+    } else {
+        gstore<C>(lamb, cellS, __builtin_nanf(""));  // the failure mark; lambda_1..12 kept
+    }
+    project_invariants(f0, fp, fm, u, T, G, !failed);
 
     const C eps = eps_sum<S, C>(d, rho, f0, fp, fm, pk, VelSeq{}) * C(1.0 / kQ);
     int br = 0;
@@ -535,7 +553,6 @@ __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const 
     // a cell whose multipliers were not found is not collided (omega = 0
     // against the finite values the solver leaves): gathered values stored
     // unchanged, multipliers kept for the next warm start
-    const bool failed = status == kFailed;
     C omega = o0;
     omega = br == 1 ? o1 : omega;
     omega = br == 2 ? o2 : omega;
@@ -552,15 +569,11 @@ __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const 
         pk.put(i, hf + omega * ((feq - C(d.shift_w[i])) - hf));
         pk.put(kQ + i, hg + omega * ((geq - C(d.shift_w[kQ + i])) - hg));
     }
-    if (!failed) {
-#pragma unroll
-        for (int k = 0; k < kM; ++k) gstore<C>(lamb + (uint64_t)k * nS64, cellS, lam[k]);
-    }
 
     acc[0] += iters;
     acc[1] = iters > acc[1] ? iters : acc[1];
     acc[2] += failed;
-    acc[3] += status == kConvergedCold;
+    acc[3] += status == kConvergedCold || (failed && !marked);  // cold restarts tried
     acc[4] += !failed && br == 0;
     acc[5] += !failed && br == 1;
     acc[6] += !failed && br == 2;
@@ -803,13 +816,36 @@ struct Park {
     }
 };
 
-// the two dword transfers of one double per lane into LDS row `row`
-__device__ __forceinline__ void dma8(gcbyte *gaddr, lds_u32 *row)
+__device__ __forceinline__ gcbyte *splane(gcbyte *p)
 {
-    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)gaddr,
+    __asm__ volatile("" : "+s"(p));
+    return p;
+}
+
+// the two dword transfers of one double per lane into LDS row `row`: low
+// words from base + off, high words from (base + 4) + off, both a uniform
+// base plus the same 32-bit lane offset (no per-lane 64-bit address)
+__device__ __forceinline__ void dma8(gcbyte *base, uint32_t off, lds_u32 *row)
+{
+    gcbyte *lo = splane(base);
+    gcbyte *hi = splane(base + 4);
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(lo + off),
                                      (void __attribute__((address_space(3))) *)row, 4, 0, 0);
-    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(gaddr + 4),
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(hi + off),
                                      (void __attribute__((address_space(3))) *)(row + kSegment), 4, 0, 0);
+}
+
+// byte offsets of the pull sources x - c, c = -3..3, along each axis
+__device__ __forceinline__ void source_offsets(const SlotDesc &d, int x, int y, int z, uint32_t (&Xo)[7],
+                                               uint32_t (&Yo)[7], uint32_t (&Zo)[7])
+{
+    const uint32_t nx = (uint32_t)d.nx, nxy = (uint32_t)d.nx * (uint32_t)d.ny;
+#pragma unroll
+    for (int c = -3; c <= 3; ++c) {
+        Xo[c + 3] = (uint32_t)source_coord(x, c, d.nx, d.axis[0] == kAxisPeriodic, d.neumann_lo[0], d.neumann_hi[0]) * 8u;
+        Yo[c + 3] = (uint32_t)source_coord(y, c, d.ny, d.axis[1] == kAxisPeriodic, d.neumann_lo[1], d.neumann_hi[1]) * nx * 8u;
+        Zo[c + 3] = (uint32_t)source_coord(z, c, d.nz, d.axis[2] == kAxisPeriodic, d.neumann_lo[2], d.neumann_hi[2]) * nxy * 8u;
+    }
 }
 
 // gather of one cell's 78 values (rows: the wave's low words of row 0);
@@ -820,16 +856,10 @@ __device__ __forceinline__ void gather(const SlotDesc &d, gcbyte *srcb, int x, i
     const uint64_t nS64 = (uint64_t)d.n * 8;
     const uint32_t nS = (uint32_t)nS64;
     const uint32_t cellS = cell * 8u;
-    const uint32_t nx = (uint32_t)d.nx, nxy = (uint32_t)d.nx * (uint32_t)d.ny;
     uint32_t Xo[7], Yo[7], Zo[7];
-#pragma unroll
-    for (int c = -3; c <= 3; ++c) {
-        Xo[c + 3] = (uint32_t)source_coord(x, c, d.nx, d.axis[0] == kAxisPeriodic, d.neumann_lo[0], d.neumann_hi[0]) * 8u;
-        Yo[c + 3] = (uint32_t)source_coord(y, c, d.ny, d.axis[1] == kAxisPeriodic, d.neumann_lo[1], d.neumann_hi[1]) * nx * 8u;
-        Zo[c + 3] = (uint32_t)source_coord(z, c, d.nz, d.axis[2] == kAxisPeriodic, d.neumann_lo[2], d.neumann_hi[2]) * nxy * 8u;
-    }
-    dma8(srcb + cellS, rows);
-    dma8(srcb + (uint64_t)kQ * nS64 + cellS, rows + kQ * kRowWords);
+    source_offsets(d, x, y, z, Xo, Yo, Zo);
+    dma8(srcb, cellS, rows);
+    dma8(srcb + (uint64_t)kQ * nS64, cellS, rows + kQ * kRowWords);
 #pragma unroll
     for (int p = 0; p < kPairs; ++p) {
         const int a = 2 * p + 1, b = 2 * p + 2;
@@ -842,10 +872,10 @@ __device__ __forceinline__ void gather(const SlotDesc &d, gcbyte *srcb, int x, i
         ob = copy ? nS + cellS : ob;
         gcbyte *bf = srcb + (uint64_t)a * nS64;
         gcbyte *bg = srcb + (uint64_t)(kQ + a) * nS64;
-        dma8(bf + oa, rows + a * kRowWords);
-        dma8(bf + ob, rows + b * kRowWords);
-        dma8(bg + oa, rows + (kQ + a) * kRowWords);
-        dma8(bg + ob, rows + (kQ + b) * kRowWords);
+        dma8(bf, oa, rows + a * kRowWords);
+        dma8(bf, ob, rows + b * kRowWords);
+        dma8(bg, oa, rows + (kQ + a) * kRowWords);
+        dma8(bg, ob, rows + (kQ + b) * kRowWords);
     }
 }
 
@@ -889,8 +919,20 @@ __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const 
 
     C f0, fp[kPairs], fm[kPairs];
     int iters = 0;
-    C resid[5];
-    const int status = solve_multipliers<C>(u, T, lam, f0, fp, fm, C(d.tol), d.maxit, d.maxit_cold, iters, resid);
+    C G[kM];
+    // a NaN lambda_0 marks a cell that had no equilibrium in the previous
+    // step: its warm start normalises the other multipliers and it is not
+    // restarted cold
+    const bool marked = !(lam[0] == lam[0]);
+    const int status = solve_multipliers<C>(u, T, lam, f0, fp, fm, C(d.tol), d.maxit, d.maxit_cold,
+                                            marked ? kStartMarked : kStartWarm, iters, G);
+    const bool failed = status == kFailed;
+    if (!failed) {
+#pragma unroll
+        for (int k = 0; k < kM; ++k) gstore<C>(splane(lamb + (uint64_t)k * nL64), cellL, lam[k]);
+    } else {
+        gstore<C>(splane(lamb), cellL, __builtin_nan(""));  // the failure mark; lambda_1..12 kept
+    }
 
     // Knudsen sensor over f (Eq. eq:DeltaAvg) and relaxation branch (Eq. eq:alpha)
     C eps = C(0);
@@ -906,7 +948,6 @@ __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const 
     // a cell whose multipliers were not found is not collided (omega = 0
     // against the finite values the solver leaves): gathered values stored
     // unchanged, multipliers kept for the next warm start
-    const bool failed = status == kFailed;
     C omega = d.omega[0];
     omega = br == 1 ? d.omega[1] : omega;
     omega = br == 2 ? d.omega[2] : omega;
@@ -923,16 +964,12 @@ __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const 
         pk.put(i, hf + omega * (feq - hf));
         pk.put(kQ + i, hg + omega * (geq - hg));
     }
-    if (!failed) {
-#pragma unroll
-        for (int k = 0; k < kM; ++k) gstore<C>(splane(lamb + (uint64_t)k * nL64), cellL, lam[k]);
-    }
 
     if constexpr (kStats) {
         acc[0] += iters;
         acc[1] = iters > acc[1] ? iters : acc[1];
         acc[2] += failed;
-        acc[3] += status == kConvergedCold;
+        acc[3] += status == kConvergedCold || (failed && !marked);  // cold restarts tried
         acc[4] += !failed && br == 0;
         acc[5] += !failed && br == 1;
         acc[6] += !failed && br == 2;
@@ -1054,11 +1091,10 @@ __global__ __launch_bounds__(256) void init_kernel(SlotDesc d, const double *__r
     const double u[3] = {fields[d.n + cell], fields[2 * d.n + cell], fields[3 * d.n + cell]};
     const double T = fields[4 * d.n + cell];
     double lam[kM], f0, fp[kPairs], fm[kPairs];
-    cold_guess(u, T, lam);
     int iters = 0;
     const int maxit = d.maxit_cold;
-    double resid[5];
-    const int st = solve_multipliers<double>(u, T, lam, f0, fp, fm, d.tol, maxit, maxit, iters, resid);
+    double G[kM];
+    const int st = solve_multipliers<double>(u, T, lam, f0, fp, fm, d.tol, maxit, maxit, kStartCold, iters, G);
     if (st == kFailed) atomicAdd(failed, 1ull);
     const double dT = d.delta * T;
     S *b0 = static_cast<S *>(d.buf[0]);
@@ -1092,10 +1128,9 @@ __global__ void single_equilibrium_kernel(double rho, double ux, double uy, doub
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     const double u[3] = {ux, uy, uz};
     double lam[kM], f0, fp[kPairs], fm[kPairs];
-    cold_guess(u, T, lam);
     int iters = 0;
-    double resid[5];
-    *status = solve_multipliers<double>(u, T, lam, f0, fp, fm, tol, maxit, maxit, iters, resid);
+    double G[kM];
+    *status = solve_multipliers<double>(u, T, lam, f0, fp, fm, tol, maxit, maxit, kStartCold, iters, G);
     for (int i = 0; i < kQ; ++i)
         out[i] = rho * ((i == 0) ? f0 : (((i - 1) & 1) == 0 ? fp[(i - 1) >> 1] : fm[(i - 1) >> 1]));
     for (int k = 0; k < kM; ++k) out[kQ + k] = lam[k];
@@ -1355,6 +1390,7 @@ hipError_t launch_moments(int storage, const SlotDesc &d, int parity, double *ou
 }
 
 int moments_partial_blocks(int64_t n) { return (int)((n + 255) / 256); }
+
 
 hipError_t launch_zero(int64_t *p, int64_t count, hipStream_t st)
 {

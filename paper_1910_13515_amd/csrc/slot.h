@@ -51,12 +51,6 @@ struct SlotDesc {
     float shell_inv_scale[2][6];
     // sums of the shift weights: mass, momentum (3), energy sum f|xi|^2 + g
     float ref_mass, ref_mom[3], ref_energy;
-    // FP32 arithmetic: projection of the invariants' residual (rest-state
-    // weights per shell at T_ref per unit density, inverse of the 2x2
-    // mass/energy block {i00, i01, i11}, and 1 / sum_i w_i xi_x^2)
-    float proj_w[6];
-    float proj_inv[3];
-    float proj_inv_w2;
     // shifted storage with unequal shift weights of opposite velocities
     // (a stream-shifted solve with obstacles): a half-way bounce-back gathers
     // the stored deviation of the opposite velocity, which becomes the

@@ -30,10 +30,10 @@ import numpy as np
 from . import lbm, precision_study
 
 
-def run(steps=20000, scale=1.0, storage="fp64", chunk=1000, log=None):
+def run(steps=20000, scale=1.0, storage="fp64", chunk=1000, log=None, shift_ref=0):
     import torch
     shape, solid, kw = precision_study.airfoil_case(scale)
-    s = lbm.Solver(shape, solid=solid, storage=storage, **kw)
+    s = lbm.Solver(shape, solid=solid, storage=storage, shift_ref=shift_ref, **kw)
     done = 0
     while done < steps:
         k = min(chunk, steps - done)
@@ -62,12 +62,17 @@ def summarize(shape, solid, eps, iters, near=8.0):
     from scipy import ndimage
     dist = ndimage.distance_transform_edt(solid.reshape(ny, nx) == 0).reshape(-1)[fluid]
     active = fin & (e >= 1e-2)
-    xs = (np.arange(nx * ny) % nx)[fluid][active]
+    xall = (np.arange(nx * ny) % nx)[fluid]
+    xs = xall[active]
+    # the free stream ahead of the bow shock: the first 40% of the domain
+    # (the leading edge sits at half its length)
+    upstream = fin & (xall < 0.4 * nx)
     return {
         "updated_cells": int(fluid.sum()),
         "newton_updates": {"histogram_0_to_4_and_more": hist, "mean": float(it[ok].mean()), "max": int(it[ok].max()),
                            "share_zero": float(np.mean(it[ok] == 0)), "cells_without_equilibrium": int(np.sum(~ok))},
         "alpha_branch_share": [float(np.mean(br == k)) for k in range(4)],
+        "upstream_share_alpha_above_1": float(np.mean(e[upstream] >= 1e-2)) if upstream.any() else 0.0,
         "sensor": {"share_active": float(active.mean()),
                    f"share_of_active_within_{near:g}_cells_of_the_airfoil": float(np.mean(dist[active] <= near))
                    if active.any() else 0.0,
@@ -103,15 +108,20 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--storage", default="fp64", choices=["fp64", "fp32s", "fp16s"])
     ap.add_argument("--png", default=None)
+    ap.add_argument("--shift-ref", type=int, default=0, choices=[0, 1],
+                    help="reduced precision: deviations from the rest weights (0) or the free stream (1)")
+    ap.add_argument("--save", default=None, help="write eps and iterations per cell to this .npz")
     args = ap.parse_args()
     import torch
     if not torch.cuda.is_available():
         raise SystemExit("the map needs a GPU")
     torch.cuda.set_device(0)
     shape, solid, eps, iters = run(args.steps, args.scale, args.storage,
-                                   log=lambda m: print("#", m, file=sys.stderr, flush=True))
-    res = {"case": "airfoil", "storage": args.storage, "steps": args.steps, "scale": args.scale,
-           **summarize(shape, solid, eps, iters)}
+                                   log=lambda m: print("#", m, file=sys.stderr, flush=True), shift_ref=args.shift_ref)
+    res = {"case": "airfoil", "storage": args.storage, "shift_ref": args.shift_ref, "steps": args.steps,
+           "scale": args.scale, **summarize(shape, solid, eps, iters)}
+    if args.save:
+        np.savez_compressed(args.save, eps=eps, iters=iters)
     if args.png:
         save_png(args.png, shape, solid, eps, iters)
     print(json.dumps(res), flush=True)
