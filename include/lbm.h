@@ -186,6 +186,18 @@ int lbm_step(lbm_ctx *ctx, int32_t nsteps, lbm_step_stats *stats);
  * LBM_E_NONFINITE if any fluid-cell moment is not finite. */
 int lbm_moments(lbm_ctx *ctx, double *out_host, double *totals);
 
+/* For callers that cannot allocate device memory at the point of the call
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * it): lbm_moments with the per-cell fields written to caller-owned device
+ * memory, dev_out (5*N doubles, SoA as lbm_moments, required), and the
+ * reduction scratch (block partials and totals) in a static array of the
+ * library instead of the context's arena; totals (nullable, host) as
+ * lbm_moments.  Grids of at most 524288 cells (larger ones: LBM_E_INVAL).
+ * Calls no allocating routine.  Every call on one GPU shares that GPU's
+ * scratch: calls that overlap on one GPU (two threads, two streams) race.
+ * Synchronises the context's stream. */
+int lbm_moments_noalloc(lbm_ctx *ctx, double *dev_out, double *totals);
+
 /* Per-cell diagnostics of the next step, from the current state, which is
  * left unchanged: the Knudsen sensor eps of Eq. (eq:DeltaAvg), whose maps
  * Sec. 4 shows for the airfoil (Fig. fig:naca-knudsen), and the number of

@@ -21,6 +21,14 @@ hipError_t launch_moments(int storage, const SlotDesc &d, int parity, double *ou
                           hipStream_t st);
 int moments_partial_blocks(int64_t n);
 
+// lbm_moments_noalloc: grids up to this many cells (the partials of one
+// moments_kernel block per 256 cells fit the static scratch), on up to this
+// many devices
+constexpr int64_t kNoallocMaxCells = 524288;
+constexpr int kNoallocMaxDevices = 64;
+// device address of the static scratch on the current device: kNoallocMaxCells
+// / 256 * 5 partials, then 5 totals
+hipError_t noalloc_scratch(double **ptr);
 hipError_t launch_zero(int64_t *p, int64_t count, hipStream_t st);
 hipError_t launch_reduce_stats(const int64_t *partial, int nwaves, int64_t *out, hipStream_t st);
 hipError_t launch_decode_pop(int storage, const SlotDesc &d, int parity, int pop, double *out, hipStream_t st);

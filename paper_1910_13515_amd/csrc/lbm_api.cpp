@@ -566,6 +566,28 @@ int lbm_moments(lbm_ctx *c, double *out_host, double *totals)
     return LBM_OK;
 }
 
+int lbm_moments_noalloc(lbm_ctx *c, double *dev_out, double *totals)
+{
+    if (!c) return fail(nullptr, LBM_E_INVAL, "ctx is NULL");
+    if (!dev_out) return fail(c, LBM_E_INVAL, "dev_out is NULL (5*N doubles of device memory are required)");
+    const int64_t n = c->desc.n;
+    if (n > kNoallocMaxCells)
+        return fail(c, LBM_E_INVAL, "lbm_moments_noalloc takes grids of at most " + std::to_string(kNoallocMaxCells) +
+                                        " cells; this one has " + std::to_string(n) + " (use lbm_moments)");
+    double *scr = nullptr;
+    HIP_TRY(c, noalloc_scratch(&scr));
+    const int64_t nb = (kNoallocMaxCells + 255) / 256;
+    HIP_TRY(c, launch_moments(c->storage, c->desc, (int)(c->steps & 1), dev_out, scr, scr + nb * 5, c->stream));
+    double t[5];
+    HIP_TRY(c, hipMemcpyAsync(t, scr + nb * 5, sizeof(t), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (totals)
+        for (int k = 0; k < 5; ++k) totals[k] = t[k];
+    for (int k = 0; k < 5; ++k)
+        if (!std::isfinite(t[k])) return fail(c, LBM_E_NONFINITE, "non-finite moments in fluid cells");
+    return LBM_OK;
+}
+
 int lbm_diagnostics(lbm_ctx *c, double *eps_out, int32_t *iters_out)
 {
     if (!c) return fail(nullptr, LBM_E_INVAL, "ctx is NULL");

@@ -19,6 +19,8 @@
 // meet in the same L2.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "equilibrium.h"
 #include "slot.h"
 
@@ -1391,6 +1393,32 @@ hipError_t launch_moments(int storage, const SlotDesc &d, int parity, double *ou
 
 int moments_partial_blocks(int64_t n) { return (int)((n + 255) / 256); }
 
+// Scratch of lbm_moments_noalloc: the per-block partial totals of
+// moments_kernel (one block per 256 cells) followed by the reduced totals,
+// for grids of up to kNoallocMaxCells cells.  Each GPU the library runs on
+// holds its own copy until the process ends.  In host code the name is a
+// host-side stand-in, never a device address: host code uses only the
+// address noalloc_scratch() looks up per device.
+__device__ __align__(256) static double scratch[(kNoallocMaxCells / 256) * 5 + 8];
+
+hipError_t noalloc_scratch(double **ptr)
+{
+    static std::mutex mu;
+    static void *addr[kNoallocMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kNoallocMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = static_cast<double *>(addr[dev]);
+    return hipSuccess;
+}
 
 hipError_t launch_zero(int64_t *p, int64_t count, hipStream_t st)
 {

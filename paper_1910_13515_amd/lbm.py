@@ -36,7 +36,7 @@ LBM_FACE_EQUILIBRIUM = 1
 LBM_FACE_NEUMANN = 2
 
 EXPORTED = ["lbm_version", "lbm_velocities", "lbm_required_bytes", "lbm_create", "lbm_step", "lbm_moments",
-            "lbm_diagnostics",
+            "lbm_moments_noalloc", "lbm_diagnostics",
             "lbm_get_state", "lbm_set_state", "lbm_get_info", "lbm_destroy", "lbm_last_error",
             "lbm_pool_overhead_bytes", "lbm_pool_create", "lbm_pool_admit", "lbm_pool_launch", "lbm_pool_wait",
             "lbm_pool_run", "lbm_pool_slot_progress", "lbm_pool_moments", "lbm_pool_release", "lbm_pool_get_info",
@@ -114,6 +114,8 @@ def load() -> ctypes.CDLL:
     L.lbm_step.argtypes = [vp, i32, ctypes.POINTER(lbm_step_stats)]
     L.lbm_moments.restype = ctypes.c_int
     L.lbm_moments.argtypes = [vp, vp, vp]
+    L.lbm_moments_noalloc.restype = ctypes.c_int
+    L.lbm_moments_noalloc.argtypes = [vp, vp, vp]
     L.lbm_diagnostics.restype = ctypes.c_int
     L.lbm_diagnostics.argtypes = [vp, vp, vp]
     L.lbm_get_state.restype = ctypes.c_int
@@ -209,6 +211,17 @@ def lbm_moments(ctx, n: int, fields: bool = True):
     if code != LBM_E_NONFINITE:
         _check(code, ctx)
     return (None if out is None else out.reshape(5, n)), tot, code
+
+
+def lbm_moments_noalloc(ctx, dev_out_ptr: int):
+    """Totals (5 doubles) of the current state; the 5*N per-cell fields go to
+    the caller's device buffer at dev_out_ptr (e.g. a torch float64 tensor's
+    data_ptr()).  No device allocation anywhere in the call."""
+    tot = np.empty(5)
+    code = load().lbm_moments_noalloc(ctx, ctypes.c_void_p(dev_out_ptr), _ptr(tot))
+    if code != LBM_E_NONFINITE:
+        _check(code, ctx)
+    return tot, code
 
 
 def lbm_diagnostics(ctx, n: int):
