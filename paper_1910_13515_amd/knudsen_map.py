@@ -30,10 +30,11 @@ import numpy as np
 from . import lbm, precision_study
 
 
-def run(steps=20000, scale=1.0, storage="fp64", chunk=1000, log=None, shift_ref=0):
+def run(steps=20000, scale=1.0, storage="fp64", chunk=1000, log=None, shift_ref=0, newton_tol=0.0, kn_relax=True):
     import torch
     shape, solid, kw = precision_study.airfoil_case(scale)
-    s = lbm.Solver(shape, solid=solid, storage=storage, shift_ref=shift_ref, **kw)
+    kw = dict(kw, kn_relax=kn_relax)
+    s = lbm.Solver(shape, solid=solid, storage=storage, shift_ref=shift_ref, newton_tol=newton_tol, **kw)
     done = 0
     while done < steps:
         k = min(chunk, steps - done)
@@ -111,14 +112,19 @@ def main():
     ap.add_argument("--shift-ref", type=int, default=0, choices=[0, 1],
                     help="reduced precision: deviations from the rest weights (0) or the free stream (1)")
     ap.add_argument("--save", default=None, help="write eps and iterations per cell to this .npz")
+    ap.add_argument("--newton-tol", type=float, default=0.0, help="0: the library default of the storage mode")
+    ap.add_argument("--plain-bgk", action="store_true", help="alpha(eps) off (the sensor is still reported)")
     args = ap.parse_args()
     import torch
     if not torch.cuda.is_available():
         raise SystemExit("the map needs a GPU")
     torch.cuda.set_device(0)
     shape, solid, eps, iters = run(args.steps, args.scale, args.storage,
-                                   log=lambda m: print("#", m, file=sys.stderr, flush=True), shift_ref=args.shift_ref)
-    res = {"case": "airfoil", "storage": args.storage, "shift_ref": args.shift_ref, "steps": args.steps,
+                                   log=lambda m: print("#", m, file=sys.stderr, flush=True), shift_ref=args.shift_ref,
+                                   newton_tol=args.newton_tol, kn_relax=not args.plain_bgk)
+    res = {"case": "airfoil", "storage": args.storage, "shift_ref": args.shift_ref, "newton_tol": args.newton_tol,
+           "kn_relax": not args.plain_bgk,
+           "steps": args.steps,
            "scale": args.scale, **summarize(shape, solid, eps, iters)}
     if args.save:
         np.savez_compressed(args.save, eps=eps, iters=iters)

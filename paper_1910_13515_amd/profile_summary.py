@@ -104,10 +104,10 @@ def counter_total(root, sub, counter, select):
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4.0
 
 
-def sq_counters(root):
-    """Mean SQ instruction counts per dispatch of each step kernel (optional run)."""
+def sq_counters(root, sub="pmc_sq"):
+    """Mean SQ counts per dispatch of each step kernel (optional runs)."""
     try:
-        path = _one(root, "pmc_sq/**/tgv128_counter_collection.csv")
+        path = _one(root, sub + "/**/tgv128_counter_collection.csv")
     except FileNotFoundError:
         return {}
     sums, counts = {}, {}
@@ -165,6 +165,20 @@ def summarize(root, commands=None):
             for c in ("SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_WAVES"):
                 if c in sq[m]:
                     v[c.lower()] = sq[m][c]
+    # where the waves' resident cycles go (optional second run): the share
+    # spent issuing VALU and LDS instructions and waiting on a dependency
+    sq2 = sq_counters(root, "pmc_sq2")
+    for m, v in modes.items():
+        w = sq2.get(m, {}).get("SQ_WAVE_CYCLES")
+        if w:
+            for c in ("SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS", "SQ_WAIT_INST_ANY", "SQ_LDS_BANK_CONFLICT",
+                      "SQ_BUSY_CYCLES"):
+                if c in sq2[m]:
+                    v[c.lower()] = sq2[m][c]
+            v["wave_cycles"] = w
+            v["valu_active_share"] = sq2[m].get("SQ_ACTIVE_INST_VALU", 0.0) / w
+            v["lds_active_share"] = sq2[m].get("SQ_ACTIVE_INST_LDS", 0.0) / w
+            v["wait_share"] = sq2[m].get("SQ_WAIT_INST_ANY", 0.0) / w
     data = {"kernel_hash": bench.kernel_hash(), "workload": "periodic 128^3 Taylor-Green vortex, Ma 0.5, Re 1600",
             "cells_per_launch": CELLS,
             "calibration": {"copy_bytes_each_way": COPY_BYTES, "copies": COPY_REPS,
@@ -196,6 +210,17 @@ def summarize(root, commands=None):
             if "valu_instr_per_cell" in v:
                 lines.append(f"| {m} | {v['valu_instr_per_cell']:.0f} | {v['valu_issue_floor_us']:.0f} | "
                              f"{v['avg_ns'] / 1e3:.0f} | {v['valu_issue_frac']:.2f} |")
+    if any("wave_cycles" in v for v in modes.values()):
+        lines += ["", "Where a wave's resident cycles go (rocprofv3 SQ_ACTIVE_INST_VALU, SQ_ACTIVE_INST_LDS, "
+                  "SQ_WAIT_INST_ANY over SQ_WAVE_CYCLES, summed over the dispatch's waves), with the waves resident "
+                  "per SIMD (SQ_WAVES per dispatch over the 1024 SIMDs, per pass of the persistent grid):", "",
+                  "| storage | waves per dispatch | VALU-issuing share | LDS-issuing share | waiting on a dependency | "
+                  "LDS bank conflicts |", "|---|---|---|---|---|---|"]
+        for m, v in modes.items():
+            if "wave_cycles" in v:
+                lines.append(f"| {m} | {v.get('sq_waves', float('nan')):.0f} | {v['valu_active_share']:.2f} | "
+                             f"{v['lds_active_share']:.3f} | {v['wait_share']:.2f} | "
+                             f"{v.get('sq_lds_bank_conflict', 0.0):.0f} |")
     c = data["calibration"]
     lines += ["", "Counter calibration (plain device copy of 1 GiB, `bench.py --copy-probe`): "
               f"FETCH_SIZE reads {c['fetch_kib_per_copy']:.0f} KiB per copy dispatch (factor {c['fetch_factor']:.3f}), "
