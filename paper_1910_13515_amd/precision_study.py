@@ -15,6 +15,12 @@ the relaxation factor alpha(eps) of one further step are reported per mode.
     python -m paper_1910_13515_amd.precision_study --case airfoil [--steps 20000] [--scale 1]
     python -m paper_1910_13515_amd.precision_study --case sphere  [--steps 2000]  [--scale 1] [--mach 1.5]
     python -m paper_1910_13515_amd.precision_study --case tgv     [--steps 1000]  [--mach 0.5] [--plain-bgk]
+    python -m paper_1910_13515_amd.precision_study --case airfoil --average 5000 --modes fp64,fp64:1e-13,fp32s
+
+``--average N`` compares time averages over the last N steps instead of end
+states (a chaotic wake makes end states of two correct runs differ by as much
+as round-off lets them), with the bow shock's position on a few rows ahead of
+the body and the alpha(eps) branch shares over the window.
 
 ``--scale`` shrinks the domain and the body together (for quick checks).
 ``--plain-bgk`` turns the Knudsen-dependent relaxation off in every mode, so
@@ -102,8 +108,55 @@ def parse_mode(mode: str):
     return storage, int(ref == "stream"), float(tol) if tol else 0.0
 
 
-def run(shape, solid, kw, storage, steps, chunk=1000, log=None):
-    """Runs one mode (see parse_mode); returns (fields[5, N], summary)."""
+def shock_front(rho, shape, x_end: int, y: int, z: int = 0, rho_inf: float = 1.0) -> float:
+    """x of the bow shock on the grid row (y, z), scanned over x < x_end:
+    going downstream from the inflow, where the density first reaches halfway
+    between the free-stream value and the row's maximum over the scan (the
+    shock's mid-point), interpolated linearly between cells.  NaN when the
+    row has no such rise."""
+    nx, ny, nz = shape
+    row = np.asarray(rho).reshape(nz, ny, nx)[z, y, :x_end]
+    if row.size < 2:
+        return float("nan")
+    half = rho_inf + 0.5 * (row.max() - rho_inf)
+    idx = np.nonzero(row >= half)[0]
+    if idx.size == 0 or idx[0] == 0 or row.max() <= rho_inf * 1.01:
+        return float("nan")
+    i = int(idx[0])
+    return float(i - 1 + (half - row[i - 1]) / (row[i] - row[i - 1]))
+
+
+def front_rows(case: str, shape, scale: float):
+    """(x of the body's front, [(label, y, z, x_end), ...]): the rows on which
+    the bow shock is located, each scanned up to x_end: the stagnation row up
+    to the body, rows an eighth and a quarter chord (airfoil) or half a radius
+    and a radius (sphere) off it up to half a chord (a radius) further, as the
+    shock bends back away from the axis."""
+    nx, ny, nz = shape
+    if case == "airfoil":
+        c = 256.0 * scale
+        x0 = int(np.floor(nx / 2.0))
+        offs = [("stagnation", 0, x0), ("+c/8", int(round(c / 8)), x0 + int(c / 2)),
+                ("-c/8", -int(round(c / 8)), x0 + int(c / 2)), ("+c/4", int(round(c / 4)), x0 + int(c / 2)),
+                ("-c/4", -int(round(c / 4)), x0 + int(c / 2))]
+        return x0, [(lab, ny // 2 + d, 0, xe) for lab, d, xe in offs]
+    if case == "sphere":
+        r = 24.0 * scale
+        x0 = int(np.floor(128.0 * scale - r))
+        xc = int(np.floor(128.0 * scale))
+        offs = [("stagnation", 0, x0), ("+r/2", int(round(r / 2)), xc), ("-r/2", -int(round(r / 2)), xc),
+                ("+r", int(round(r)), xc), ("-r", -int(round(r)), xc)]
+        return x0, [(lab, ny // 2 + d, nz // 2, xe) for lab, d, xe in offs]
+    return None, []
+
+
+def run(shape, solid, kw, storage, steps, chunk=1000, log=None, average=0, sample=50):
+    """Runs one mode (see parse_mode); returns (fields[5, N], summary).
+
+    With ``average`` > 0 the fields returned are the time averages of
+    (rho, u, T) over the last ``average`` steps, sampled every ``sample``
+    steps, and the summary carries the alpha(eps) branch shares over that
+    window; otherwise they are the end state."""
     import torch
     mode = storage
     storage, shift_ref, tol = parse_mode(mode)
@@ -113,12 +166,28 @@ def run(shape, solid, kw, storage, steps, chunk=1000, log=None):
     t0 = time.perf_counter()
     failed = 0
     done = 0
+    start_avg = steps - average if average > 0 else steps + 1
+    acc, nacc, alpha_win, upd_win = None, 0, np.zeros(4), 0
+    stepping = 0.0
     while done < steps:
         k = min(chunk, steps - done)
+        if done >= start_avg:
+            k = min(k, sample)
+        elif done + k > start_avg:
+            k = start_avg - done
+        ts = time.perf_counter()
         st = s.step(k, stats=True)
+        torch.cuda.synchronize()
+        stepping += time.perf_counter() - ts
         failed += st.failed
         done += k
-        if log:
+        if done > start_avg:
+            alpha_win += np.array(st.alpha_hist[:4], dtype=np.float64)
+            upd_win += st.cell_updates
+            f, _ = s.moments()
+            acc = f.copy() if acc is None else acc + f
+            nacc += 1
+        if log and (done % chunk == 0 or done == steps):
             log(f"{mode}: {done}/{steps} steps, Newton failures so far {failed}")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -129,14 +198,19 @@ def run(shape, solid, kw, storage, steps, chunk=1000, log=None):
     del s
     torch.cuda.empty_cache()
     upd = max(1, st.cell_updates)
-    return fields, {
+    summary = {
         "storage": storage, "shift": "free stream" if shift_ref else "rest weights", "newton_tol": tol,
-        "tau": info.tau, "seconds": dt, "glups": info.cells * steps / dt / 1e9,
+        "tau": info.tau, "seconds": dt, "glups": info.cells * steps / stepping / 1e9,
         "newton_failures": int(failed), "newton_iterations_per_cell": st.iterations / upd,
         "newton_max_iterations": int(st.max_iterations),
         "alpha_fraction": [a / upd for a in st.alpha_hist], "totals": [float(v) for v in tot],
         "finite": bool(np.all(np.isfinite(tot))),
     }
+    if nacc:
+        fields = acc / nacc
+        summary["window"] = {"steps": average, "samples": nacc,
+                             "alpha_fraction": (alpha_win / max(1, upd_win)).tolist()}
+    return fields, summary
 
 
 def errors(f, ref, fluid):
@@ -192,8 +266,13 @@ def curve(case: str, every: int, steps: int | None = None, scale: float = 1.0, m
             "columns": cols, "rows": rows}
 
 
+def mach_field(f, gamma):
+    """Local Mach number |u| / sqrt(gamma T) of a fields array [5, N]."""
+    return np.sqrt((f[1:4] ** 2).sum(0) / (gamma * np.maximum(f[4], 1e-300)))
+
+
 def study(case: str, steps: int | None = None, scale: float = 1.0, modes=None, mach: float | None = None, log=None,
-          plain_bgk: bool = False):
+          plain_bgk: bool = False, average: int = 0, sample: int = 50, chunk: int = 1000):
     make, default_modes, default_steps = CASES[case]
     steps = default_steps if steps is None else steps
     modes = default_modes if modes is None else modes
@@ -206,15 +285,32 @@ def study(case: str, steps: int | None = None, scale: float = 1.0, modes=None, m
                "params": {k: v for k, v in kw.items() if k not in ("faces", "fields")},
                "faces": list(kw.get("faces", (PER,) * 6)), "modes": {}}
     fields = {}
+    x_body, rows = front_rows(case, shape, scale)
+    if average > 0:
+        results["window"] = {"steps": average, "sample_every": sample,
+                             "fields": "time averages of (rho, u, T) over the window"}
     for m in modes:
-        f, summ = run(shape, solid, kw, m, steps, log=log)
+        f, summ = run(shape, solid, kw, m, steps, chunk=chunk, log=log, average=average, sample=sample)
         fields[m] = f
+        if x_body is not None:
+            summ["shock_x"] = {lab: shock_front(f[0], shape, xe, y, z) for lab, y, z, xe in rows}
+            summ["standoff"] = x_body - summ["shock_x"]["stagnation"]
         results["modes"][m] = summ
     ref = fields.get("fp64")
     if ref is not None:
         for m in modes:
             if m != "fp64":
-                results["modes"][m]["vs_fp64"] = errors(fields[m], ref, fluid)
+                e = errors(fields[m], ref, fluid)
+                ma, ma_ref = mach_field(fields[m], kw["gamma"])[fluid], mach_field(ref, kw["gamma"])[fluid]
+                e["l2_mach"] = float(np.linalg.norm(ma - ma_ref) / np.linalg.norm(ma_ref))
+                e["max_mach"] = float(np.max(np.abs(ma - ma_ref)))
+                if x_body is not None:
+                    sx, sx_ref = results["modes"][m]["shock_x"], results["modes"]["fp64"]["shock_x"]
+                    e["shock_x_shift"] = {k: sx[k] - sx_ref[k] for k in sx}
+                    if "window" in results["modes"][m]:
+                        a, a_ref = (results["modes"][q]["window"]["alpha_fraction"] for q in (m, "fp64"))
+                        e["alpha_share_diff"] = [x - y for x, y in zip(a, a_ref)]
+                results["modes"][m]["vs_fp64"] = e
     if "fp32s" in fields and "fp16s" in fields:
         results["modes"]["fp16s"]["vs_fp32s"] = errors(fields["fp16s"], fields["fp32s"], fluid)
     return results
@@ -232,6 +328,11 @@ def main():
     ap.add_argument("--mach", type=float, default=None, help="default: the case's own (1.5; TGV 0.5)")
     ap.add_argument("--plain-bgk", action="store_true",
                     help="relax every cell with 1/tau (alpha(eps) off), in every mode including the FP64 reference")
+    ap.add_argument("--average", type=int, default=0,
+                    help="compare time averages over the last N steps (sampled every --sample steps) instead of "
+                         "the end state, and report the alpha(eps) branch shares over that window")
+    ap.add_argument("--sample", type=int, default=50)
+    ap.add_argument("--chunk", type=int, default=1000, help="steps per launch batch (and per progress line)")
     ap.add_argument("--every", type=int, default=0,
                     help="instead: run all modes side by side and report their errors every N steps")
     args = ap.parse_args()
@@ -246,7 +347,8 @@ def main():
         print(json.dumps(res), flush=True)
         return
     res = study(args.case, args.steps, args.scale, modes, args.mach,
-                log=lambda m: print("#", m, file=sys.stderr, flush=True), plain_bgk=args.plain_bgk)
+                log=lambda m: print("#", m, file=sys.stderr, flush=True), plain_bgk=args.plain_bgk,
+                average=args.average, sample=args.sample, chunk=args.chunk)
     print(json.dumps(res), flush=True)
 
 

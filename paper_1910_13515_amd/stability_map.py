@@ -10,6 +10,7 @@ reports for each run whether it stayed finite and how many cell updates found
 no equilibrium (in the first and second halves of the run).
 
     python -m paper_1910_13515_amd.stability_map [--steps 10000] [--scale 1] [--storage fp64]
+        [--grid 1.5:7500,1.5:1e9] [--relax both|plain|eps]
 
 Prints one JSON object.
 """
@@ -60,10 +61,10 @@ def run_case(mach, reynolds, kn_relax, steps, scale, storage, chunk=250, log=Non
             "stable": finite and done == steps and failed[1] == 0}
 
 
-def sweep(steps=10000, scale=1.0, storage="fp64", grid=GRID, log=None):
+def sweep(steps=10000, scale=1.0, storage="fp64", grid=GRID, log=None, relax=(False, True)):
     out = []
     for mach, re in grid:
-        for kn in (False, True):
+        for kn in relax:
             r = run_case(mach, re, kn, steps, scale, storage, log=log)
             if log:
                 log(json.dumps(r))
@@ -77,13 +78,17 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--storage", default="fp64", choices=["fp64", "fp32s", "fp16s"])
     ap.add_argument("--grid", default=None, help="Ma:Re pairs, comma-separated (default: the four of the sweep)")
+    ap.add_argument("--relax", default="both", choices=["both", "plain", "eps"],
+                    help="plain BGK, BGK with alpha(eps), or both for every (Ma, Re)")
     args = ap.parse_args()
+    relax = {"both": (False, True), "plain": (False,), "eps": (True,)}[args.relax]
     grid = GRID if not args.grid else [tuple(float(v) for v in g.split(":")) for g in args.grid.split(",")]
     import torch
     if not torch.cuda.is_available():
         raise SystemExit("the stability map needs a GPU")
     torch.cuda.set_device(0)
-    res = sweep(args.steps, args.scale, args.storage, grid, log=lambda m: print("#", m, file=sys.stderr, flush=True))
+    res = sweep(args.steps, args.scale, args.storage, grid, log=lambda m: print("#", m, file=sys.stderr, flush=True),
+                relax=relax)
     print(json.dumps({"case": "airfoil", "scale": args.scale, "steps": args.steps, "storage": args.storage,
                       "T_ref": precision_study.T_OBSTACLE, "runs": res}), flush=True)
 
