@@ -10,7 +10,9 @@ all cells (f and g).  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode fp64|fp32s|fp16s]
                   [--n 128] [--no-modes] [--no-cpu] [--no-serving]
-                  [--serving-requests 40] [--serving-rate 3.0] [--serving-only]
+                  [--serving-requests 40] [--serving-rate 1.75] [--serving-only]
+  python bench.py --serving-only --serving-requests 200 --serving-rate 1.75 \
+                  --serving-seeds 2024,2025,2026   (run-to-run spread of the serving figures)
   python bench.py --copy-probe   (plain device copy of 1 GiB x 5, used to
                                   calibrate the FETCH_SIZE / WRITE_SIZE counters)
 
@@ -103,7 +105,8 @@ def run_case(case, mode, develop, steps):
     from paper_1910_13515_amd import lbm, precision_study
     make = {"airfoil": precision_study.airfoil_case, "sphere": precision_study.sphere_case}[case]
     shape, solid, kw = make(1.0)
-    s = lbm.Solver(shape, solid=solid, storage=mode, **kw)
+    storage, shift_ref, _ = precision_study.parse_mode(mode)
+    s = lbm.Solver(shape, solid=solid, storage=storage, shift_ref=shift_ref, **kw)
     cells = int(np.prod(shape))
     done = 0
     while done < develop:
@@ -124,7 +127,7 @@ def run_case(case, mode, develop, steps):
     del s
     torch.cuda.empty_cache()
     ms_step = ms / steps
-    bpc = BYTES_PER_CELL[mode] + 8
+    bpc = BYTES_PER_CELL[storage] + 8
     achieved = bpc * cells / (ms_step * 1e-3) / 1e9
     return {"workload": f"{case} {'x'.join(map(str, shape))}, Ma {kw['mach']}, Re {kw['reynolds']:g}, "
                         f"T_ref {kw['T_ref']:.4g}, {mode}, timed after {develop} steps",
@@ -235,6 +238,21 @@ def serving_leg(count, rate, seed=2024, arena_gib=96, max_slots=64, graph_steps=
         print(f"# serving one-at-a-time: p50 {seq['p50_s']:.3f} s p99 {seq['p99_s']:.3f} s "
               f"{seq['aggregate_glups']:.3f} GLUPS", file=sys.stderr, flush=True)
         out["one_at_a_time"] = seq
+    return out
+
+
+def serving_spread(runs):
+    """Min, mean and max over runs (one per trace seed) of each side's p50,
+    p99 and aggregate GLUPS, and of the pool's gain over one at a time."""
+    out = {}
+    for side in ("batched", "one_at_a_time"):
+        for key in ("p50_s", "p99_s", "aggregate_glups"):
+            v = [r[side][key] for r in runs]
+            out[f"{side}.{key}"] = {"min": min(v), "mean": sum(v) / len(v), "max": max(v)}
+    for key, better in (("p50_s", "lower"), ("p99_s", "lower"), ("aggregate_glups", "higher")):
+        g = [(r["one_at_a_time"][key] / r["batched"][key]) if better == "lower"
+             else (r["batched"][key] / r["one_at_a_time"][key]) for r in runs]
+        out[f"gain.{key}"] = {"min": min(g), "mean": sum(g) / len(g), "max": max(g)}
     return out
 
 
@@ -371,6 +389,9 @@ def main():
                     help="with --serving-only: run one side of the comparison alone (for profiling)")
     ap.add_argument("--serving-sched", default="vft", choices=["vft", "srpt", "all"],
                     help="round selection of the pool (with --serving-only)")
+    ap.add_argument("--serving-seeds", default=None,
+                    help="with --serving-only: comma-separated trace seeds, one full comparison each, and the "
+                         "spread of p50, p99 and throughput over them")
     ap.add_argument("--cpu-table", action="store_true",
                     help="time the FP64 oracle on the workloads' configurations instead (host only)")
     ap.add_argument("--cpu-table-short", action="store_true", help="with --cpu-table: the short set (Sod, TGV 32^3)")
@@ -393,6 +414,11 @@ def main():
     from paper_1910_13515_amd import lbm
     lbm.load()
     if args.serving_only:
+        if args.serving_seeds:
+            runs = [serving_leg(args.serving_requests, args.serving_rate, seed=int(sd), sched=args.serving_sched)
+                    for sd in args.serving_seeds.split(",")]
+            print(json.dumps({"serving_runs": runs, "spread": serving_spread(runs)}), flush=True)
+            return
         print(json.dumps({"serving": serving_leg(args.serving_requests, args.serving_rate, sched=args.serving_sched,
                                                  batched=args.serving_side != "sequential",
                                                  sequential=args.serving_side != "batched")}), flush=True)
@@ -412,9 +438,10 @@ def main():
     configs = {}
     if not args.no_configs:
         # the airfoil compares FP32-shifted storage with FP64, the sphere
-        # FP16-shifted with FP32 and FP64 (each at its full size)
+        # FP16-shifted (on the rest weights, and on the free stream's
+        # equilibrium) with FP32 and FP64 (each at its full size)
         for case, modes_c, develop, steps_c in (("airfoil", ("fp32s", "fp64"), 2000, 200),
-                                                ("sphere", ("fp16s", "fp32s", "fp64"), 200, 20)):
+                                                ("sphere", ("fp16s", "fp16s@stream", "fp32s", "fp64"), 500, 20)):
             for m in modes_c:
                 r = run_case(case, m, develop, steps_c)
                 print(f"# {case} {m}: {r['glups']:.3f} GLUPS, {r['ms_per_step']:.3f} ms/step", file=sys.stderr,

@@ -107,6 +107,15 @@ typedef struct {
     const double *init_rho;    /* initial fields (N, 3N as ux|uy|uz, N) or NULL for the reference state */
     const double *init_u;
     const double *init_T;
+    int32_t root_finder;       /* multipliers found by 0: Newton-Raphson (Sec. 3, the algorithm table of
+                                  Sec. 5); 1: a secant method that never evaluates the Jacobian of G, the
+                                  gradient-free side of the choice Sec. 6 leaves open (FP64 storage only;
+                                  not in the pool): limited-memory BFGS on the convex dual whose gradient
+                                  is G, memory 3, started from the inverse of a model Jacobian (the rest
+                                  Jacobian at T_ref, scaled to the cell's T and shifted to its u); same
+                                  stopping rule, floor stop, stall and failure handling as Newton; a step is
+                                  accepted when it lowers ||G||_2 or, along a descent direction, the dual by
+                                  1e-4 t G.d; newton_maxit 0 selects 100 for it */
 } lbm_params;
 
 /* Per-call statistics of lbm_step(), summed over fluid cells and steps. */

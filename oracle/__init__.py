@@ -17,6 +17,12 @@ Parity status of each function (what pins it, see ``tests/test_oracle_*.py``):
     against the Navier-Stokes rate; sound speed sqrt(gamma T); Sod shock tube
     against the exact Riemann solution; streaming permutation against numpy.roll.
   * orc_moments: the totals are checked against direct sums in the tests.
+  * orc_equilibrium_secant / root_finder 1 (the secant variant): the shift
+    matrix against the shifted basis at random points; the model Jacobian
+    against Gauss-Hermite moments of the continuous Maxwellian; convergence
+    to the same (unique) equilibrium as the 32-digit solve; its first update
+    at rest equal to Newton's; a step equal to the Newton step within the
+    stopping bound.
 """
 from __future__ import annotations
 
@@ -61,6 +67,7 @@ class _Params(ctypes.Structure):
         ("gamma", ctypes.c_double), ("tau", ctypes.c_double), ("newton_tol", ctypes.c_double),
         ("solid", ctypes.c_void_p),
         ("floor_rule", ctypes.c_int32), ("skip_cold_after_failure", ctypes.c_int32),
+        ("root_finder", ctypes.c_int32), ("model_T", ctypes.c_double),
     ]
 
 
@@ -86,6 +93,11 @@ def lib(variant: str = "plain"):
         L.orc_equilibrium.restype = ctypes.c_int
         L.orc_equilibrium.argtypes = [ctypes.c_double, dp, ctypes.c_double, ctypes.c_double, dp, ctypes.c_int,
                                       ctypes.c_double, ctypes.c_int, dp, dp]
+        L.orc_equilibrium_secant.restype = ctypes.c_int
+        L.orc_equilibrium_secant.argtypes = [ctypes.c_double, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                             dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp]
+        L.orc_model_jacobian.restype = ctypes.c_int
+        L.orc_model_jacobian.argtypes = [dp, ctypes.c_double, ctypes.c_double, ctypes.c_void_p, dp, dp]
         L.orc_init.restype = ctypes.c_int64
         L.orc_step.restype = None
         L.orc_moments.restype = None
@@ -122,6 +134,33 @@ def equilibrium(rho, u, T, gamma=1.4, lam=None, tol=1e-13, maxit=100):
     return feq, geq, lam, it
 
 
+def equilibrium_secant(rho, u, T, T_ref, gamma=1.4, lam=None, tol=1e-13, maxit=100):
+    """Equilibrium of one cell by the secant variant (model Jacobian on the
+    rest equilibrium at T_ref).  Returns (feq, geq, lam, iterations)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    cold = lam is None
+    lam = np.zeros(NL) if cold else np.array(lam, dtype=np.float64)
+    feq = np.zeros(NQ)
+    geq = np.zeros(NQ)
+    it = lib().orc_equilibrium_secant(float(rho), _dptr(u), float(T), float(T_ref), float(gamma), _dptr(lam),
+                                      int(cold), float(tol), int(maxit), _dptr(feq), _dptr(geq))
+    return feq, geq, lam, it
+
+
+def model_jacobian(u, T, T_ref, J_rest=None):
+    """(J_model, A(u)) of the secant variant; J_rest (13 x 13) replaces the
+    lattice's rest Jacobian at T_ref when given."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    J = np.zeros((NL, NL))
+    A = np.zeros((NL, NL))
+    jr = None if J_rest is None else np.ascontiguousarray(J_rest, dtype=np.float64)
+    rc = lib().orc_model_jacobian(_dptr(u), float(T), float(T_ref), None if jr is None else _ptr(jr), _dptr(J),
+                                  _dptr(A))
+    if rc != 0:
+        raise RuntimeError("no rest equilibrium at this temperature")
+    return J, A
+
+
 def shear_response(T: float, du: float = 1e-4) -> float:
     """K(T) = d/du_y sum_i f^eq_i xi_x^2 xi_y at rest, per unit density, by a
     central difference of this oracle's equilibrium.  The BGK lattice step has
@@ -146,7 +185,7 @@ class Oracle:
 
     def __init__(self, nx, ny, nz, gamma=1.4, tau=0.6, kn_relax=True, faces=(0,) * 6, solid=None,
                  newton_tol=1e-13, newton_maxit=30, variant="plain", floor_rule=True,
-                 skip_cold_after_failure=True):
+                 skip_cold_after_failure=True, root_finder=0, model_T=0.5):
         self.L = lib(variant)
         self.shape = (nx, ny, nz)
         self.n = nx * ny * nz
@@ -167,6 +206,8 @@ class Oracle:
         p.solid = _ptr(self.solid) if self.solid is not None else None
         p.floor_rule = int(bool(floor_rule))
         p.skip_cold_after_failure = int(bool(skip_cold_after_failure))
+        p.root_finder = int(root_finder)
+        p.model_T = float(model_T)
         self.p = p
         self.f = np.zeros(NQ * self.n)
         self.g = np.zeros(NQ * self.n)

@@ -15,7 +15,9 @@
  *     with the 13 constraints of Eq. (eq:13constraints);
  *   - exponential equilibrium: Sec. 2, Eq. (eq:discrete-equilibrium);
  *   - Newton-Raphson for the Lagrange multipliers: Sec. 3 and the algorithm
- *     table of Sec. 5 (warm start from the previous time step);
+ *     table of Sec. 5 (warm start from the previous time step); a secant
+ *     (limited-memory BFGS) variant that never evaluates the Jacobian, for
+ *     the choice of root finder that Sec. 6 leaves open;
  *   - polyatomic second population: Eq. (eq:discrete-equilibrium-poly);
  *   - Knudsen sensor: Eq. (eq:DeltaAvg); relaxation factor: Eq. (eq:alpha);
  *   - BGK collide-and-stream for h = f, g with Pr = 1: Sec. 3;
@@ -296,6 +298,204 @@ static int newton(const double m[NL], double lam[NL], double feq[NQ], double tol
 }
 
 /* ------------------------------------------------------------------------ */
+/* Variant of the root finder (Sec. 6 names the choice between gradient-based */
+/* and gradient-free algorithms as an open question): a secant method that   */
+/* never evaluates the Jacobian of G.                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Powers of the basis functions in xi: 0 for 1, 1 for xi_a, 2 for the
+ * products, 3 for xi_a |xi|^2. */
+static const int BASIS_DEGREE[NL] = {0, 1, 1, 1, 2, 2, 2, 2, 2, 2, 3, 3, 3};
+
+/* A(v) with phi(xi + v) = A(v) phi(xi) for every xi: the span of the 13 basis
+ * functions is closed under shifts of xi (the shift of xi_a |xi|^2 stays a
+ * polynomial of degree 3 whose cubic part is xi_a |xi|^2 again).  Built from
+ * that definition: on the 39 velocities Phi (39 x 13) has rank 13, so
+ * A(v)^T = (Phi^T Phi)^-1 Phi^T Phi_v with Phi_v[i][k] = phi_k(xi_i + v). */
+static void shift_matrix(const double v[3], double A[NL][NL])
+{
+    double M[NL][NL], col[NL], x[NL];
+    double Pv[NQ][NL];
+    int i, k, l;
+    for (i = 0; i < NQ; ++i) {
+        double c[3] = {VEL[i][0] + v[0], VEL[i][1] + v[1], VEL[i][2] + v[2]};
+        basis(c, Pv[i]);
+    }
+    for (k = 0; k < NL; ++k)
+        for (l = 0; l < NL; ++l) {
+            double t = 0.0;
+            for (i = 0; i < NQ; ++i) t += PHI[i][k] * PHI[i][l];
+            M[k][l] = t;
+        }
+    for (l = 0; l < NL; ++l) {  /* column l of A^T is row l of A */
+        double Mc[NL][NL];
+        for (k = 0; k < NL; ++k) {
+            double t = 0.0;
+            for (i = 0; i < NQ; ++i) t += PHI[i][k] * Pv[i][l];
+            col[k] = t;
+        }
+        memcpy(Mc, M, sizeof(M));
+        cholesky_solve(Mc, col, x);
+        for (k = 0; k < NL; ++k) A[l][k] = x[k];
+    }
+}
+
+/* Model of the Jacobian at (u, T): J_model = A(u) D J_rest D A(u)^T with
+ * D = diag((T / T_ref)^(degree_k / 2)).  For the continuous Maxwellian this
+ * is exact: its moment matrix E[phi phi^T] at (u, T) is that of rest at T_ref
+ * with xi scaled by sqrt(T / T_ref) and shifted by u.  J_rest is the Jacobian
+ * at the lattice's own rest equilibrium at T_ref, so at u = 0, T = T_ref the
+ * model is the true Jacobian there. */
+static void model_jacobian(const double u[3], double T, double T_ref, const double Jrest[NL][NL], double Jm[NL][NL])
+{
+    double A[NL][NL], B[NL][NL], Dg[NL];
+    int k, l, a;
+    shift_matrix(u, A);
+    for (k = 0; k < NL; ++k) Dg[k] = pow(T / T_ref, 0.5 * BASIS_DEGREE[k]);
+    /* B = A D J_rest D */
+    for (k = 0; k < NL; ++k)
+        for (l = 0; l < NL; ++l) {
+            double t = 0.0;
+            for (a = 0; a < NL; ++a) t += A[k][a] * Dg[a] * Jrest[a][l] * Dg[l];
+            B[k][l] = t;
+        }
+    for (k = 0; k < NL; ++k)
+        for (l = 0; l < NL; ++l) {
+            double t = 0.0;
+            for (a = 0; a < NL; ++a) t += B[k][a] * A[l][a];
+            Jm[k][l] = t;
+        }
+}
+
+/* Jacobian of the lattice's rest equilibrium at temperature T_ref (per unit
+ * density), the equilibrium found by this file's Newton from the cold guess. */
+static int rest_jacobian(double T_ref, double Jrest[NL][NL])
+{
+    double m[NL], lam[NL], feq[NQ];
+    const double u0[3] = {0.0, 0.0, 0.0};
+    mb_targets(u0, T_ref, m);
+    cold_guess(u0, T_ref, lam);
+    if (newton(m, lam, feq, 1e-15, 100, 1, NULL) < 0) return -1;
+    jacobian(feq, Jrest);
+    return 0;
+}
+
+#define SECANT_MEMORY 3
+
+/* Limited-memory BFGS (Nocedal and Wright, Numerical Optimization, the
+ * two-loop recursion) for G(lambda) = 0, G being the gradient of the convex
+ * dual Phi(lambda) = sum_i exp(phi_i . lambda) - lambda . m, so that J is
+ * Phi's Hessian.  Only residuals G are evaluated: the direction d = H G uses
+ * the last SECANT_MEMORY pairs s = lambda_new - lambda_old, y = G_new - G_old
+ * (kept only when s . y > 0) on top of H0 = J_model^-1 (model_jacobian).  The
+ * step is lambda - t d, t = 1, 1/2, ..., 2^-39; a trial is accepted when it
+ * lowers the Euclidean norm of G (the Newton rule) or, for a descent
+ * direction (G . d > 0), when it lowers Phi by at least 1e-4 t G . d
+ * (Armijo), which a positive definite H guarantees for small t.  Stopping
+ * rule, round-off floor stop (floor_rule) and stall as in newton().  Returns
+ * the number of accepted updates, or -1 (cap, stall, value not finite). */
+static int secant(const double m[NL], double lam[NL], double feq[NQ], double tol, int maxit, int floor_rule,
+                  const double Jm[NL][NL], int64_t *evals)
+{
+    double G[NL], Gt[NL], ft[NQ], trial[NL], d[NL];
+    double S[SECANT_MEMORY][NL], Y[SECANT_MEMORY][NL], rho_s[SECANT_MEMORY];
+    double scale = 1.0, phi, lm;
+    int it, k, ls, np = 0;
+    int64_t ne = 1;
+    for (k = 0; k < NL; ++k)
+        if (fabs(m[k]) > scale) scale = fabs(m[k]);
+    equilibrium_and_residual(lam, m, feq, G);
+    phi = 0.0;
+    for (k = 0; k < NQ; ++k) phi += feq[k];
+    lm = 0.0;
+    for (k = 0; k < NL; ++k) lm += lam[k] * m[k];
+    phi -= lm;
+    for (it = 0;; ++it) {
+        double r = norm_inf(G);
+        double n0, gd, t = 1.0, q[NL], al[SECANT_MEMORY];
+        double Jc[NL][NL];
+        int j, accepted = 0;
+        if (!isfinite(r)) break;
+        if (r <= tol * scale) {
+            if (evals) *evals += ne;
+            return it;
+        }
+        if (it >= maxit) break;
+        /* two-loop recursion: d = H G */
+        for (k = 0; k < NL; ++k) q[k] = G[k];
+        for (j = np - 1; j >= 0; --j) {
+            double t2 = 0.0;
+            for (k = 0; k < NL; ++k) t2 += S[j][k] * q[k];
+            al[j] = rho_s[j] * t2;
+            for (k = 0; k < NL; ++k) q[k] -= al[j] * Y[j][k];
+        }
+        memcpy(Jc, Jm, sizeof(Jc));
+        if (cholesky_solve(Jc, q, d) != 0) break;
+        for (j = 0; j < np; ++j) {
+            double b = 0.0;
+            for (k = 0; k < NL; ++k) b += Y[j][k] * d[k];
+            b *= rho_s[j];
+            for (k = 0; k < NL; ++k) d[k] += S[j][k] * (al[j] - b);
+        }
+        n0 = norm_2(G);
+        gd = 0.0;
+        for (k = 0; k < NL; ++k) gd += G[k] * d[k];
+        for (ls = 0; ls < 40; ++ls) {
+            double pt = 0.0;
+            for (k = 0; k < NL; ++k) trial[k] = lam[k] - t * d[k];
+            equilibrium_and_residual(trial, m, ft, Gt);
+            ne += 1;
+            for (k = 0; k < NQ; ++k) pt += ft[k];
+            lm = 0.0;
+            for (k = 0; k < NL; ++k) lm += trial[k] * m[k];
+            pt -= lm;
+            if (norm_2(Gt) < n0 || (gd > 0.0 && pt <= phi - 1e-4 * t * gd)) {
+                accepted = 1;
+                phi = pt;
+                break;
+            }
+            if (ls == 0 && floor_rule && r <= 8.0 * tol * scale && norm_inf(Gt) <= 8.0 * tol * scale) {
+                for (k = 0; k < NL; ++k) lam[k] = trial[k];
+                for (k = 0; k < NQ; ++k) feq[k] = ft[k];
+                if (evals) *evals += ne;
+                return it + 1;
+            }
+            t *= 0.5;
+        }
+        if (!accepted) break;
+        {
+            double sv[NL], yv[NL], sy = 0.0;
+            for (k = 0; k < NL; ++k) {
+                sv[k] = -t * d[k];  /* the step taken */
+                yv[k] = Gt[k] - G[k];
+                sy += sv[k] * yv[k];
+            }
+            if (sy > 0.0) {
+                if (np == SECANT_MEMORY) {
+                    for (j = 1; j < SECANT_MEMORY; ++j) {
+                        memcpy(S[j - 1], S[j], sizeof(S[j]));
+                        memcpy(Y[j - 1], Y[j], sizeof(Y[j]));
+                        rho_s[j - 1] = rho_s[j];
+                    }
+                    np -= 1;
+                }
+                memcpy(S[np], sv, sizeof(sv));
+                memcpy(Y[np], yv, sizeof(yv));
+                rho_s[np] = 1.0 / sy;
+                np += 1;
+            }
+        }
+        for (k = 0; k < NL; ++k) {
+            lam[k] = trial[k];
+            G[k] = Gt[k];
+        }
+        for (k = 0; k < NQ; ++k) feq[k] = ft[k];
+    }
+    if (evals) *evals += ne;
+    return -1;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Public interface (ctypes)                                                */
 /* ------------------------------------------------------------------------ */
 
@@ -314,6 +514,8 @@ typedef struct {
     /* readings that the pins switch off to show what they change (1 = on) */
     int32_t floor_rule;    /* stop at the round-off floor (see newton) */
     int32_t skip_cold_after_failure; /* a cell that failed the previous step is not restarted cold */
+    int32_t root_finder;   /* 0: Newton-Raphson (the paper's); 1: the secant variant */
+    double model_T;        /* root_finder 1: temperature of the rest Jacobian of its model */
 } orc_params;
 
 typedef struct {
@@ -505,6 +707,52 @@ static int alpha_branch(double eps)
 /* Initial state: every cell holds the equilibrium of its (rho, u, T) field,
  * computed with the cold start; the multipliers are stored for the warm start.
  * Returns the number of cells whose Newton did not converge. */
+/* The secant variant for one cell: as orc_equilibrium, with the model
+ * Jacobian built on the rest equilibrium at T_ref.  Returns the number of
+ * accepted updates or -1. */
+int orc_equilibrium_secant(double rho, const double *u, double T, double T_ref, double gamma, double *lam, int cold,
+                           double tol, int maxit, double *feq_out, double *geq_out)
+{
+    double m[NL], feq[NQ], Jrest[NL][NL], Jm[NL][NL];
+    double delta = 2.0 * heat_capacity(gamma) - DIM;
+    int it, i;
+    make_tables();
+    if (rest_jacobian(T_ref, Jrest) != 0) return -2;
+    model_jacobian(u, T, T_ref, (const double(*)[NL])Jrest, Jm);
+    mb_targets(u, T, m);
+    if (cold) cold_guess(u, T, lam);
+    it = secant(m, lam, feq, tol, maxit, 1, (const double(*)[NL])Jm, NULL);
+    for (i = 0; i < NQ; ++i) {
+        if (feq_out) feq_out[i] = rho * feq[i];
+        if (geq_out) geq_out[i] = delta * T * rho * feq[i];
+    }
+    return it;
+}
+
+/* The secant variant's model Jacobian at (u, T) (row-major 13 x 13) built
+ * on Jrest_in (row-major, or NULL for the lattice's rest Jacobian at T_ref),
+ * and the shift matrix A(u) of phi(xi + u) = A(u) phi(xi). */
+int orc_model_jacobian(const double *u, double T, double T_ref, const double *Jrest_in, double *J_out, double *A_out)
+{
+    double Jrest[NL][NL], Jm[NL][NL], A[NL][NL];
+    int k, l;
+    make_tables();
+    if (Jrest_in) {
+        for (k = 0; k < NL; ++k)
+            for (l = 0; l < NL; ++l) Jrest[k][l] = Jrest_in[k * NL + l];
+    } else if (rest_jacobian(T_ref, Jrest) != 0) {
+        return -1;
+    }
+    model_jacobian(u, T, T_ref, (const double(*)[NL])Jrest, Jm);
+    shift_matrix(u, A);
+    for (k = 0; k < NL; ++k)
+        for (l = 0; l < NL; ++l) {
+            if (J_out) J_out[k * NL + l] = Jm[k][l];
+            if (A_out) A_out[k * NL + l] = A[k][l];
+        }
+    return 0;
+}
+
 int64_t orc_init(const orc_params *p, const double *rho, const double *u, const double *T, double *f, double *g,
                  double *lam)
 {
@@ -547,7 +795,9 @@ void orc_step(const orc_params *p, const double *f, const double *g, const doubl
     int64_t s_it = 0, s_max = 0, s_fail = 0, s_cold = 0, h0 = 0, h1 = 0, h2 = 0, h3 = 0, s_ev = 0;
     double Cv = heat_capacity(p->gamma);
     double delta = 2.0 * Cv - DIM;
+    double Jrest[NL][NL];
     make_tables();
+    if (p->root_finder == 1 && rest_jacobian(p->model_T, Jrest) != 0) return;
 #pragma omp parallel for schedule(dynamic, 64) \
     reduction(+ : s_it, s_fail, s_cold, h0, h1, h2, h3, s_ev) reduction(max : s_max)
     for (c = 0; c < n; ++c) {
@@ -557,6 +807,7 @@ void orc_step(const orc_params *p, const double *f, const double *g, const doubl
         int i, k, it, br, bounced, marked;
         double fi[NQ], gi[NQ], l[NL], m[NL], feq[NQ], geq[NQ];
         double rho, u[3], T, eps, tau_eff, omega;
+        double Jm[NL][NL];
         if (cell_type(p, x, y, z) != CELL_FLUID) {
             for (i = 0; i < NQ; ++i) {
                 fo[i * n + c] = f[i * n + c];
@@ -581,7 +832,12 @@ void orc_step(const orc_params *p, const double *f, const double *g, const doubl
         for (k = 0; k < NL; ++k) l[k] = lam[k * n + c];
         marked = isnan(l[0]);
         if (marked) normalise(l);
-        it = newton(m, l, feq, p->newton_tol, p->newton_maxit, p->floor_rule, &s_ev);
+        if (p->root_finder == 1) {
+            model_jacobian(u, T, p->model_T, (const double(*)[NL])Jrest, Jm);
+            it = secant(m, l, feq, p->newton_tol, p->newton_maxit, p->floor_rule, (const double(*)[NL])Jm, &s_ev);
+        } else {
+            it = newton(m, l, feq, p->newton_tol, p->newton_maxit, p->floor_rule, &s_ev);
+        }
         if (it < 0) {
             /* reading: a failed warm start is retried once from the cold
              * start before the cell is counted as failed, unless the cell
@@ -591,8 +847,12 @@ void orc_step(const orc_params *p, const double *f, const double *g, const doubl
             if (!(marked && p->skip_cold_after_failure)) {
                 s_cold += 1;
                 cold_guess(u, T, l);
-                it2 = newton(m, l, feq, p->newton_tol, p->newton_maxit > 100 ? p->newton_maxit : 100,
-                             p->floor_rule, &s_ev);
+                if (p->root_finder == 1)
+                    it2 = secant(m, l, feq, p->newton_tol, p->newton_maxit > 100 ? p->newton_maxit : 100,
+                                 p->floor_rule, (const double(*)[NL])Jm, &s_ev);
+                else
+                    it2 = newton(m, l, feq, p->newton_tol, p->newton_maxit > 100 ? p->newton_maxit : 100,
+                                 p->floor_rule, &s_ev);
             }
             if (it2 < 0) {
                 /* reading: where no multipliers reproduce the 13 targets the

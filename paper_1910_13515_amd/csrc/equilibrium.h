@@ -376,6 +376,276 @@ __device__ __forceinline__ int solve_multipliers(const C u[3], C T, C lam[kM], C
     return status;
 }
 
+// ---------------------------------------------------------------------------
+// Secant variant of the root finder (Sec. 6 leaves the choice between
+// gradient-based and gradient-free algorithms open): the Jacobian of G is
+// never evaluated.  G is the gradient of the convex dual
+// Phi(lam) = sum_i exp(phi_i . lam) - lam . m, and limited-memory BFGS builds
+// the inverse Jacobian from the steps s and residual changes y of the last
+// kSecantMemory accepted updates, on top of a model inverse H0.
+
+constexpr int kSecantMemory = 3;
+
+// r = H0 v with H0 the inverse of the model Jacobian A(u) D J_rest D A(u)^T:
+// J_rest is the Jacobian of the rest equilibrium at T_ref, D = diag(s^-deg_k)
+// with s = sqrt(T_ref / T) and deg_k the degree of basis function k in xi,
+// and A(w) the shift of the basis, phi(xi + w) = A(w) phi(xi) (the span of
+// the 13 functions is closed under shifts).  Since A(u)^-1 = A(-u),
+//     H0 = A(w)^T D^-1 H_rest D^-1 A(w),  w = -u,
+// applied here factor by factor; H_rest = J_rest^-1 has the cubic-symmetric
+// blocks of h (see SlotDesc::qn_h).  For the continuous Maxwellian this
+// model is exact.
+template <class C>
+__device__ __forceinline__ void model_inverse_apply(const double (&h)[8], C sc, const C w[3], const C v[kM],
+                                                    C r[kM])
+{
+    const C w0 = w[0], w1 = w[1], w2 = w[2];
+    const C ww = w0 * w0 + w1 * w1 + w2 * w2;
+    const C tr = v[4] + v[5] + v[6];
+    C x[kM];
+    // x = A(w) v
+    x[0] = v[0];
+    x[1] = w0 * v[0] + v[1];
+    x[2] = w1 * v[0] + v[2];
+    x[3] = w2 * v[0] + v[3];
+    x[4] = w0 * w0 * v[0] + C(2) * w0 * v[1] + v[4];
+    x[5] = w1 * w1 * v[0] + C(2) * w1 * v[2] + v[5];
+    x[6] = w2 * w2 * v[0] + C(2) * w2 * v[3] + v[6];
+    x[7] = w0 * w1 * v[0] + w1 * v[1] + w0 * v[2] + v[7];
+    x[8] = w0 * w2 * v[0] + w2 * v[1] + w0 * v[3] + v[8];
+    x[9] = w1 * w2 * v[0] + w2 * v[2] + w1 * v[3] + v[9];
+    x[10] = ww * w0 * v[0] + (C(2) * w0 * w0 + ww) * v[1] + C(2) * w0 * w1 * v[2] + C(2) * w0 * w2 * v[3] +
+            w0 * tr + C(2) * w0 * v[4] + C(2) * w1 * v[7] + C(2) * w2 * v[8] + v[10];
+    x[11] = ww * w1 * v[0] + C(2) * w1 * w0 * v[1] + (C(2) * w1 * w1 + ww) * v[2] + C(2) * w1 * w2 * v[3] +
+            w1 * tr + C(2) * w1 * v[5] + C(2) * w0 * v[7] + C(2) * w2 * v[9] + v[11];
+    x[12] = ww * w2 * v[0] + C(2) * w2 * w0 * v[1] + C(2) * w2 * w1 * v[2] + (C(2) * w2 * w2 + ww) * v[3] +
+            w2 * tr + C(2) * w2 * v[6] + C(2) * w0 * v[8] + C(2) * w1 * v[9] + v[12];
+    // D^-1, H_rest, D^-1
+    const C s1 = sc, s2 = sc * sc, s3 = s2 * sc;
+#pragma unroll
+    for (int k = 1; k <= 3; ++k) x[k] *= s1;
+#pragma unroll
+    for (int k = 4; k <= 9; ++k) x[k] *= s2;
+#pragma unroll
+    for (int k = 10; k <= 12; ++k) x[k] *= s3;
+    C y[kM];
+    const C h00 = C(h[0]), h0s = C(h[1]), hss = C(h[2]), hst = C(h[3]);
+    const C h11 = C(h[4]), h1q = C(h[5]), hqq = C(h[6]), hp = C(h[7]);
+    const C S = x[4] + x[5] + x[6];
+    y[0] = h00 * x[0] + h0s * S;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        y[4 + a] = h0s * x[0] + (hss - hst) * x[4 + a] + hst * S;
+        y[1 + a] = h11 * x[1 + a] + h1q * x[10 + a];
+        y[10 + a] = h1q * x[1 + a] + hqq * x[10 + a];
+        y[7 + a] = hp * x[7 + a];
+    }
+#pragma unroll
+    for (int k = 1; k <= 3; ++k) y[k] *= s1;
+#pragma unroll
+    for (int k = 4; k <= 9; ++k) y[k] *= s2;
+#pragma unroll
+    for (int k = 10; k <= 12; ++k) y[k] *= s3;
+    // r = A(w)^T y
+    const C wq = w0 * y[10] + w1 * y[11] + w2 * y[12];
+    r[0] = y[0] + w0 * y[1] + w1 * y[2] + w2 * y[3] + w0 * w0 * y[4] + w1 * w1 * y[5] + w2 * w2 * y[6] +
+           w0 * w1 * y[7] + w0 * w2 * y[8] + w1 * w2 * y[9] + ww * wq;
+    r[1] = y[1] + C(2) * w0 * y[4] + w1 * y[7] + w2 * y[8] + ww * y[10] + C(2) * w0 * wq;
+    r[2] = y[2] + C(2) * w1 * y[5] + w0 * y[7] + w2 * y[9] + ww * y[11] + C(2) * w1 * wq;
+    r[3] = y[3] + C(2) * w2 * y[6] + w0 * y[8] + w1 * y[9] + ww * y[12] + C(2) * w2 * wq;
+    r[4] = y[4] + wq + C(2) * w0 * y[10];
+    r[5] = y[5] + wq + C(2) * w1 * y[11];
+    r[6] = y[6] + wq + C(2) * w2 * y[12];
+    r[7] = y[7] + C(2) * w1 * y[10] + C(2) * w0 * y[11];
+    r[8] = y[8] + C(2) * w2 * y[10] + C(2) * w0 * y[12];
+    r[9] = y[9] + C(2) * w2 * y[11] + C(2) * w1 * y[12];
+    r[10] = y[10];
+    r[11] = y[11];
+    r[12] = y[12];
+}
+
+// The secant variant of solve_multipliers (same arguments, starts, stopping
+// rule, round-off floor stop, stall, cold restart and outputs; iters counts
+// accepted updates).  Direction d = H G by the two-loop recursion over the
+// stored pairs (s = -t d, the step taken, and y = G_new - G_old, kept only
+// when s . y > 0, the oldest dropped beyond kSecantMemory) on H0 =
+// model_inverse_apply; trial lam - t d, t = 1, 1/2, ..., 2^-39.  A trial is
+// accepted when it lowers ||G||_2, or, for a descent direction (G . d > 0),
+// when it lowers Phi by at least 1e-4 t G . d (Armijo on the dual, which a
+// positive definite H guarantees for small t).  A cold restart drops the
+// stored pairs.
+template <class C>
+__device__ __forceinline__ int solve_multipliers_secant(const C u[3], C T, C lam[kM], C &f0, C fp[kPairs],
+                                                        C fm[kPairs], C tol, int maxit, int maxit_cold, int start,
+                                                        int &iters, C (&G)[kM], const double (&hq)[8],
+                                                        double T_ref)
+{
+    C m[kM];
+    mb_targets(u, T, m);
+    C scale = C(1);
+#pragma unroll
+    for (int k = 0; k < kM; ++k) scale = fabs(m[k]) > scale ? fabs(m[k]) : scale;
+    const C bound = tol * scale;
+    const C h = u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + C(5) * T;
+    const C w[3] = {-u[0], -u[1], -u[2]};
+    const C sc = dsqrt(C(T_ref) / T);
+
+    C Sp[kSecantMemory][kM], Yp[kSecantMemory][kM], rs[kSecantMemory];
+#pragma unroll
+    for (int j = 0; j < kSecantMemory; ++j) {
+        rs[j] = C(0);
+#pragma unroll
+        for (int k = 0; k < kM; ++k) Sp[j][k] = Yp[j][k] = C(0);
+    }
+    int np = 0;
+    C Gacc[kM], d[kM];
+#pragma unroll
+    for (int k = 0; k < kM; ++k) Gacc[k] = d[k] = C(0);
+    C t = C(0), n0 = C(0), phi0 = C(0), gd = C(0);
+    const bool from_cold = start == kStartCold;
+    int it = 0, ls = 0, cap = from_cold ? maxit_cold : maxit;
+    bool fresh = true, cold = start != kStartWarm, floor_stop = false;
+    bool restarted = from_cold;
+    bool near = false;
+    int status = kFailed;
+    if (from_cold) maxwellian_shape(u, T, lam);
+    if (start != kStartWarm) normalise_lam0(lam);
+    for (;;) {
+        eval_exponentials(lam, f0, fp, fm);
+        {
+            C s[kPairs], a[kPairs];
+#pragma unroll
+            for (int p = 0; p < kPairs; ++p) {
+                s[p] = fp[p] + fm[p];
+                a[p] = fp[p] - fm[p];
+            }
+            residual_impl(f0, s, a, u, T, h, G, BasisSeq{});
+        }
+        C n2 = C(0), lm = C(0);
+#pragma unroll
+        for (int k = 0; k < kM; ++k) {
+            n2 += G[k] * G[k];
+            lm += lam[k] * m[k];
+        }
+        n2 = dsqrt(n2);
+        // dual objective: sum_i exp(phi_i . lam) - lam . m, the sum being G_0 + m_0
+        const C phi = (G[0] + m[0]) - lm;
+        C r = C(0);
+#pragma unroll
+        for (int k = 0; k < kM; ++k) {
+            const C g = fabs(G[k]);
+            r = (g <= r) ? r : g;
+        }
+        const bool lower = (n2 < n0) || (gd > C(0) && phi <= phi0 - C(1e-4) * t * gd);
+        floor_stop = !fresh && !lower && ls == 0 && near && r <= C(8) * bound;
+        const bool rejected = !fresh && !lower && !floor_stop;
+        if (rejected && ls < 39) {
+            t *= C(0.5);
+            ++ls;
+#pragma unroll
+            for (int k = 0; k < kM; ++k) lam[k] += t * d[k];
+            continue;
+        }
+        bool bad = rejected;
+        if (!bad) {
+            if (!fresh) {
+                ++it;
+                C sy = C(0);
+#pragma unroll
+                for (int k = 0; k < kM; ++k) sy += (-t * d[k]) * (G[k] - Gacc[k]);
+                if (sy > C(0)) {
+#pragma unroll
+                    for (int j = 0; j + 1 < kSecantMemory; ++j) {
+                        rs[j] = rs[j + 1];
+#pragma unroll
+                        for (int k = 0; k < kM; ++k) {
+                            Sp[j][k] = Sp[j + 1][k];
+                            Yp[j][k] = Yp[j + 1][k];
+                        }
+                    }
+                    rs[kSecantMemory - 1] = C(1) / sy;
+#pragma unroll
+                    for (int k = 0; k < kM; ++k) {
+                        Sp[kSecantMemory - 1][k] = -t * d[k];
+                        Yp[kSecantMemory - 1][k] = G[k] - Gacc[k];
+                    }
+                    np = np < kSecantMemory ? np + 1 : kSecantMemory;
+                }
+            }
+            fresh = false;
+            near = r <= C(8) * bound;
+            if (r <= bound || floor_stop) {
+                status = restarted ? kConvergedCold : kConverged;
+                break;
+            }
+            bad = !(r - r == C(0)) || it >= cap;
+        }
+        if (!bad) {
+            // two-loop recursion, newest pair first; pairs sit at the end
+            C q[kM], al[kSecantMemory];
+#pragma unroll
+            for (int k = 0; k < kM; ++k) q[k] = G[k];
+#pragma unroll
+            for (int j = kSecantMemory - 1; j >= 0; --j) {
+                C sq = C(0);
+#pragma unroll
+                for (int k = 0; k < kM; ++k) sq += Sp[j][k] * q[k];
+                al[j] = j >= kSecantMemory - np ? rs[j] * sq : C(0);
+#pragma unroll
+                for (int k = 0; k < kM; ++k) q[k] -= al[j] * Yp[j][k];
+            }
+            model_inverse_apply(hq, sc, w, q, d);
+#pragma unroll
+            for (int j = 0; j < kSecantMemory; ++j) {
+                C yd = C(0);
+#pragma unroll
+                for (int k = 0; k < kM; ++k) yd += Yp[j][k] * d[k];
+                const C b = j >= kSecantMemory - np ? al[j] - rs[j] * yd : C(0);
+#pragma unroll
+                for (int k = 0; k < kM; ++k) d[k] += Sp[j][k] * b;
+            }
+            gd = C(0);
+#pragma unroll
+            for (int k = 0; k < kM; ++k) gd += G[k] * d[k];
+            bad = !(gd - gd == C(0));
+        }
+        if (bad) {
+            if (cold) {
+                status = kFailed;
+                break;
+            }
+            cold = true;
+            restarted = true;
+            maxwellian_shape(u, T, lam);
+            normalise_lam0(lam);
+            it = 0;
+            ls = 0;
+            cap = maxit_cold;
+            fresh = true;
+            np = 0;
+            gd = C(0);
+            continue;
+        }
+#pragma unroll
+        for (int k = 0; k < kM; ++k) Gacc[k] = G[k];
+        t = C(1);
+        ls = 0;
+        n0 = n2;
+        phi0 = phi;
+#pragma unroll
+        for (int k = 0; k < kM; ++k) lam[k] -= d[k];
+    }
+    if (status == kFailed) {
+        f0 = C(0);
+#pragma unroll
+        for (int p = 0; p < kPairs; ++p) fp[p] = fm[p] = C(0);
+#pragma unroll
+        for (int k = 0; k < kM; ++k) G[k] = C(0);
+    }
+    iters = status == kFailed ? maxit : it;
+    return status;
+}
+
 // Remove the residuals of the five collision invariants, R = sum_i f_i psi_i
 // - target with psi = (1, xi, |xi|^2), that a solve stopped at a tolerance
 // leaves in the equilibrium f (per unit density):

@@ -10,7 +10,9 @@
 
 namespace lbm13 {
 
-hipError_t launch_step(int storage, const SlotTable *tab, int grid, int j, int64_t *stats, hipStream_t st);
+// solver: 0 Newton-Raphson, 1 the secant variant (FP64 storage only)
+hipError_t launch_step(int storage, const SlotTable *tab, int grid, int j, int64_t *stats, hipStream_t st,
+                       int solver = 0);
 const void *step_kernel_symbol(int storage);
 hipError_t launch_diag(int storage, const SlotTable *tab, int grid, int j, double *diag, hipStream_t st);
 hipError_t launch_init(int storage, const SlotDesc &d, const double *fields, unsigned long long *failed,

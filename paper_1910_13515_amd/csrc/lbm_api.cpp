@@ -99,6 +99,8 @@ std::string validate(const lbm_params *p)
         return "tau <= 0 needs reynolds > 0, length_ref > 0 and mach > 0";
     if (p->newton_maxit < 0 || p->newton_maxit > 1000) return "newton_maxit out of range";
     if (!(p->newton_tol >= 0.0) || !std::isfinite(p->newton_tol)) return "newton_tol must be finite and >= 0";
+    if (p->root_finder < 0 || p->root_finder > 1) return "root_finder must be 0 (Newton) or 1 (secant)";
+    if (p->root_finder == 1 && p->storage != LBM_STORE_FP64) return "the secant root finder needs FP64 storage";
     if (p->mach > 0.0) {
         const double du = std::sqrt(p->u_dir[0] * p->u_dir[0] + p->u_dir[1] * p->u_dir[1] + p->u_dir[2] * p->u_dir[2]);
         if (!(du > 0.0) || !std::isfinite(du)) return "u_dir must be a nonzero finite vector when mach > 0";
@@ -190,6 +192,73 @@ double shear_response(const double *w, double T)
     return a * k1 + b * k2;
 }
 
+// Model constants of the secant root finder: the inverse of the Jacobian
+// J_kl = sum_i w_i phi_ik phi_il of the rest equilibrium w (per unit
+// density) in its cubic-symmetric blocks (h00, h0s, hss, hst over
+// (1, xi_a^2); h11, h1q, hqq over (xi_a, xi_a |xi|^2); hp for xi_a xi_b).
+// Returns false if J is singular or does not have that block structure.
+bool secant_model(const double *w, double h[8])
+{
+    double J[kM][2 * kM];
+    for (int k = 0; k < kM; ++k)
+        for (int l = 0; l < 2 * kM; ++l) J[k][l] = (l - kM == k) ? 1.0 : 0.0;
+    for (int i = 0; i < kQ; ++i) {
+        const double x = vel(i, 0), y = vel(i, 1), z = vel(i, 2), q = x * x + y * y + z * z;
+        const double phi[kM] = {1, x, y, z, x * x, y * y, z * z, x * y, x * z, y * z, x * q, y * q, z * q};
+        for (int k = 0; k < kM; ++k)
+            for (int l = 0; l < kM; ++l) J[k][l] += w[i] * phi[k] * phi[l];
+    }
+    // Gauss-Jordan with partial pivoting on [J | I]
+    for (int col = 0; col < kM; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < kM; ++r)
+            if (std::fabs(J[r][col]) > std::fabs(J[piv][col])) piv = r;
+        if (!(std::fabs(J[piv][col]) > 0.0)) return false;
+        for (int l = 0; l < 2 * kM; ++l) std::swap(J[col][l], J[piv][l]);
+        const double inv = 1.0 / J[col][col];
+        for (int l = 0; l < 2 * kM; ++l) J[col][l] *= inv;
+        for (int r = 0; r < kM; ++r)
+            if (r != col) {
+                const double f = J[r][col];
+                for (int l = 0; l < 2 * kM; ++l) J[r][l] -= f * J[col][l];
+            }
+    }
+    auto H = [&](int k, int l) { return J[k][kM + l]; };
+    h[0] = H(0, 0);
+    h[1] = H(0, 4);
+    h[2] = H(4, 4);
+    h[3] = H(4, 5);
+    h[4] = H(1, 1);
+    h[5] = H(1, 10);
+    h[6] = H(10, 10);
+    h[7] = H(7, 7);
+    // the structure the kernel assumes (cubic symmetry of the lattice and of
+    // the rest weights; odd and even functions decouple)
+    double big = 0.0, dev = 0.0;
+    for (int k = 0; k < kM; ++k)
+        for (int l = 0; l < kM; ++l) {
+            const auto deg = [](int m) { return m == 0 ? 0 : m <= 3 ? 1 : m <= 9 ? 2 : 3; };
+            const auto axis = [](int m) { return m >= 1 && m <= 3 ? m - 1 : m >= 10 ? m - 10 : m >= 4 && m <= 6 ? m - 4 : -1; };
+            double ref = 0.0;
+            const bool ek = deg(k) % 2 == 0, el = deg(l) % 2 == 0;
+            if (ek && el) {
+                const bool dk = k == 0 || (k >= 4 && k <= 6), dl = l == 0 || (l >= 4 && l <= 6);
+                if (dk && dl) {
+                    if (k == 0 && l == 0) ref = h[0];
+                    else if (k == 0 || l == 0) ref = h[1];
+                    else ref = k == l ? h[2] : h[3];
+                } else if (k == l) {
+                    ref = h[7];
+                }
+            } else if (!ek && !el && axis(k) == axis(l)) {
+                ref = (k == l) ? (k <= 3 ? h[4] : h[6]) : h[5];
+            }
+            big = std::max(big, std::fabs(H(k, l)));
+            dev = std::max(dev, std::fabs(H(k, l) - ref));
+        }
+    return std::isfinite(big) && dev <= 1e-10 * big;
+}
+
 // Per-cell link mask for half-way bounce-back: bit i set when a lattice node
 // passed over by velocity i (x - k dir_i, k = 1..mult_i) is solid; bit 63 for
 // solid cells.  Computed for fluid cells only.
@@ -248,7 +317,8 @@ int create_in(lbm_ctx *c, const lbm_params *params)
     lbm_params &p = c->params;
     if (p.rho_ref == 0.0) p.rho_ref = 1.0;
     if (p.T_ref == 0.0) p.T_ref = 0.5;
-    if (p.newton_maxit == 0) p.newton_maxit = 20;
+    // the secant variant takes more (cheaper) updates than Newton
+    if (p.newton_maxit == 0) p.newton_maxit = p.root_finder == 1 ? 100 : 20;
     // FP32 arithmetic: 1e-5 of the largest target.  From the warm start one
     // Newton update reaches it in all but a few cells; tighter bounds (down
     // to the FP32 residual floor near 1e-6) add a second update to most waves
@@ -298,6 +368,10 @@ int create_in(lbm_ctx *c, const lbm_params *params)
     }
     d.has_links = params->solid != nullptr;
     d.kn_relax = p.kn_relax ? 1 : 0;
+    d.root_finder = p.root_finder;
+    d.qn_T_ref = p.T_ref;
+    if (p.root_finder == 1 && !secant_model(rest, d.qn_h))
+        return fail(c, LBM_E_NONREALIZABLE, "the rest Jacobian at T_ref is not usable for the secant root finder");
     d.maxit = p.newton_maxit;
     d.maxit_cold = std::max(p.newton_maxit, 100);
     d.parity0 = 0;
@@ -456,7 +530,7 @@ int create_in(lbm_ctx *c, const lbm_params *params)
 
 extern "C" {
 
-int32_t lbm_version(void) { return 10000; }
+int32_t lbm_version(void) { return 10100; }
 
 int lbm_velocities(int32_t *out)
 {
@@ -525,7 +599,8 @@ int lbm_step(lbm_ctx *c, int32_t nsteps, lbm_step_stats *stats)
     for (int32_t s = 0; s < nsteps; ++s) {
         const int j = (int)((c->steps + s) & 1);
         // statistics only when asked for: the kernels without them run lighter
-        HIP_TRY(c, launch_step(c->storage, c->d_table, c->grid, j, stats ? d_stats : nullptr, c->stream));
+        HIP_TRY(c, launch_step(c->storage, c->d_table, c->grid, j, stats ? d_stats : nullptr, c->stream,
+                               c->params.root_finder));
     }
     c->steps += nsteps;
     if (!stats) return LBM_OK;
@@ -955,6 +1030,7 @@ int lbm_pool_admit(lbm_pool *p, const lbm_params *params, int32_t nsteps, int32_
     if (!p) return fail(nullptr, LBM_E_INVAL, "pool is NULL");
     if (!params || !slot_out || nsteps < 0) return pool_fail(p, LBM_E_INVAL, "invalid argument");
     if (params->storage != p->storage) return pool_fail(p, LBM_E_INVAL, "storage differs from the pool's");
+    if (params->root_finder != 0) return pool_fail(p, LBM_E_INVAL, "the pool runs the Newton root finder only");
     const int64_t need = lbm_required_bytes(params);
     if (need < 0) return pool_fail(p, (int)need, lbm_last_error(nullptr));
     int slot = -1;

@@ -311,8 +311,17 @@ __device__ __forceinline__ void diag_cell(const SlotDesc &d, const S *src, int x
     C G[kM];
     // a NaN lambda_0 marks a cell that had no equilibrium in the previous step
     const bool marked = !(lam[0] == lam[0]);
-    const int status = solve_multipliers<C>(u, T, lam, f0, fp, fm, C(d.tol), d.maxit, d.maxit_cold,
+    int status;
+    if constexpr (sizeof(C) == 8) {
+        status = d.root_finder == 1
+                     ? solve_multipliers_secant<C>(u, T, lam, f0, fp, fm, C(d.tol), d.maxit, d.maxit_cold,
+                                                   marked ? kStartMarked : kStartWarm, iters, G, d.qn_h, d.qn_T_ref)
+                     : solve_multipliers<C>(u, T, lam, f0, fp, fm, C(d.tol), d.maxit, d.maxit_cold,
                                             marked ? kStartMarked : kStartWarm, iters, G);
+    } else {
+        status = solve_multipliers<C>(u, T, lam, f0, fp, fm, C(d.tol), d.maxit, d.maxit_cold,
+                                      marked ? kStartMarked : kStartWarm, iters, G);
+    }
     if constexpr (sizeof(C) == 4) {
         // FP32 arithmetic stops at a tolerance far above FP64's; make the
         // collision invariants exact so that the bias of the last Newton
@@ -881,9 +890,9 @@ __device__ __forceinline__ void gather(const SlotDesc &d, gcbyte *srcb, int x, i
     }
 }
 
-// moments, Newton, sensor and relaxation of one fluid cell whose gathered
-// values sit in LDS; the results replace them
-template <bool kStats>
+// moments, Newton (kSolver 0; 1: the secant variant), sensor and relaxation
+// of one fluid cell whose gathered values sit in LDS; the results replace them
+template <bool kStats, int kSolver>
 __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const Park &pk, int32_t (&acc)[kStatWords])
 {
     using C = double;
@@ -926,8 +935,13 @@ __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const 
     // step: its warm start normalises the other multipliers and it is not
     // restarted cold
     const bool marked = !(lam[0] == lam[0]);
-    const int status = solve_multipliers<C>(u, T, lam, f0, fp, fm, C(d.tol), d.maxit, d.maxit_cold,
-                                            marked ? kStartMarked : kStartWarm, iters, G);
+    int status;
+    if constexpr (kSolver == 0)
+        status = solve_multipliers<C>(u, T, lam, f0, fp, fm, C(d.tol), d.maxit, d.maxit_cold,
+                                      marked ? kStartMarked : kStartWarm, iters, G);
+    else
+        status = solve_multipliers_secant<C>(u, T, lam, f0, fp, fm, C(d.tol), d.maxit, d.maxit_cold,
+                                             marked ? kStartMarked : kStartWarm, iters, G, d.qn_h, d.qn_T_ref);
     const bool failed = status == kFailed;
     if (!failed) {
 #pragma unroll
@@ -982,8 +996,9 @@ __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const 
 }  // namespace f64
 
 // kStats: per-wave statistics (iterations, failures, alpha branches) into
-// stats; the variant without them keeps those registers free for the solve
-template <bool kStats>
+// stats; the variant without them keeps those registers free for the solve.
+// kSolver: 0 Newton-Raphson, 1 the secant variant of the root finder.
+template <bool kStats, int kSolver>
 __global__ __launch_bounds__(kBlockThreads, 1) void step_kernel_f64(const SlotTable *__restrict__ tab, int j,
                                                                    int64_t *__restrict__ stats)
 {
@@ -1034,7 +1049,7 @@ __global__ __launch_bounds__(kBlockThreads, 1) void step_kernel_f64(const SlotTa
         int32_t it_cell = 0;
         if (fluid) {
             const int32_t before = acc[0];
-            f64::collide<kStats>(d, cell, pk, acc);
+            f64::collide<kStats, kSolver>(d, cell, pk, acc);
             it_cell = acc[0] - before;
         }
         if constexpr (kStats) {
@@ -1321,14 +1336,21 @@ hipError_t launch_diag(int storage, const SlotTable *tab, int grid, int j, doubl
     return hipGetLastError();
 }
 
-hipError_t launch_step(int storage, const SlotTable *tab, int grid, int j, int64_t *stats, hipStream_t st)
+hipError_t launch_step(int storage, const SlotTable *tab, int grid, int j, int64_t *stats, hipStream_t st,
+                       int solver)
 {
     switch (storage) {
     case kStoreF64:
-        if (stats)
-            hipLaunchKernelGGL(step_kernel_f64<true>, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
-        else
-            hipLaunchKernelGGL(step_kernel_f64<false>, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
+        if (solver == 1) {
+            if (stats)
+                hipLaunchKernelGGL((step_kernel_f64<true, 1>), dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
+            else
+                hipLaunchKernelGGL((step_kernel_f64<false, 1>), dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
+        } else if (stats) {
+            hipLaunchKernelGGL((step_kernel_f64<true, 0>), dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
+        } else {
+            hipLaunchKernelGGL((step_kernel_f64<false, 0>), dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
+        }
         break;
     case kStoreF32:
         hipLaunchKernelGGL(step_kernel_f32, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
@@ -1346,7 +1368,7 @@ hipError_t launch_step(int storage, const SlotTable *tab, int grid, int j, int64
 const void *step_kernel_symbol(int storage)
 {
     switch (storage) {
-    case kStoreF64: return reinterpret_cast<const void *>(&step_kernel_f64<false>);
+    case kStoreF64: return reinterpret_cast<const void *>(&step_kernel_f64<false, 0>);
     case kStoreF32: return reinterpret_cast<const void *>(&step_kernel_f32);
     default: return reinterpret_cast<const void *>(&step_kernel_f16<false>);
     }

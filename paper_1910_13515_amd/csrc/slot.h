@@ -57,6 +57,15 @@ struct SlotDesc {
     // population once bb_corr[i] = w_opp(i) - w_i is added (f: 0..38, g: 39..77)
     int32_t asym_bounce;
     float bb_corr[78];
+    // root finder of the multipliers: 0 Newton-Raphson, 1 the secant variant
+    // (FP64 only), whose model Jacobian is built on the rest equilibrium at
+    // qn_T_ref; qn_h holds the inverse of that rest Jacobian in its cubic-
+    // symmetric blocks: h00, h0s, hss, hst over (1, xi_a^2); h11, h1q, hqq
+    // over (xi_a, xi_a |xi|^2) of one axis; hp for xi_a xi_b, a != b
+    int32_t root_finder;
+    int32_t pad1;
+    double qn_T_ref;
+    double qn_h[8];
 };
 
 struct SlotTable {

@@ -43,6 +43,10 @@ EXPORTED = ["lbm_version", "lbm_velocities", "lbm_required_bytes", "lbm_create",
             "lbm_pool_destroy", "lbm_pool_last_error"]
 
 
+# root finders of the multipliers: Newton-Raphson, or the secant variant
+ROOT_FINDER = {"newton": 0, "secant": 1}
+
+
 class lbm_params(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
@@ -52,7 +56,7 @@ class lbm_params(ctypes.Structure):
         ("length_ref", ctypes.c_double), ("rho_ref", ctypes.c_double), ("T_ref", ctypes.c_double),
         ("u_dir", ctypes.c_double * 3), ("tau", ctypes.c_double), ("newton_tol", ctypes.c_double),
         ("solid", ctypes.c_void_p), ("init_rho", ctypes.c_void_p), ("init_u", ctypes.c_void_p),
-        ("init_T", ctypes.c_void_p),
+        ("init_T", ctypes.c_void_p), ("root_finder", ctypes.c_int32),
     ]
 
 
@@ -262,7 +266,7 @@ def lbm_destroy(ctx):
 
 def make_params(shape, storage="fp64", gamma=1.4, mach=0.0, reynolds=0.0, length_ref=0.0, rho_ref=1.0, T_ref=0.5,
                 u_dir=(1.0, 0.0, 0.0), tau=0.0, kn_relax=True, faces=(0,) * 6, newton_tol=0.0, newton_maxit=0,
-                shift_ref=0):
+                shift_ref=0, root_finder=0):
     p = lbm_params()
     p.nx, p.ny, p.nz = (int(v) for v in shape)
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
@@ -281,6 +285,7 @@ def make_params(shape, storage="fp64", gamma=1.4, mach=0.0, reynolds=0.0, length
         p.u_dir[k] = float(u_dir[k])
     p.tau = float(tau)
     p.newton_tol = float(newton_tol)
+    p.root_finder = ROOT_FINDER[root_finder] if isinstance(root_finder, str) else int(root_finder)
     return p
 
 

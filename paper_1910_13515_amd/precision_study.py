@@ -128,10 +128,11 @@ def shock_front(rho, shape, x_end: int, y: int, z: int = 0, rho_inf: float = 1.0
 
 def front_rows(case: str, shape, scale: float):
     """(x of the body's front, [(label, y, z, x_end), ...]): the rows on which
-    the bow shock is located, each scanned up to x_end: the stagnation row up
-    to the body, rows an eighth and a quarter chord (airfoil) or half a radius
-    and a radius (sphere) off it up to half a chord (a radius) further, as the
-    shock bends back away from the axis."""
+    the bow shock is located, each scanned up to x_end.  Airfoil: the
+    stagnation row up to the leading edge, rows an eighth and a quarter chord
+    off it up to half a chord further (the shock bends back away from the
+    axis).  Sphere: rows 0, r/2 and r off the axis, each up to where it meets
+    the sphere."""
     nx, ny, nz = shape
     if case == "airfoil":
         c = 256.0 * scale
@@ -144,8 +145,10 @@ def front_rows(case: str, shape, scale: float):
         r = 24.0 * scale
         x0 = int(np.floor(128.0 * scale - r))
         xc = int(np.floor(128.0 * scale))
-        offs = [("stagnation", 0, x0), ("+r/2", int(round(r / 2)), xc), ("-r/2", -int(round(r / 2)), xc),
-                ("+r", int(round(r)), xc), ("-r", -int(round(r)), xc)]
+        # each row up to the sphere's surface on it (where the row meets it)
+        offs = [(lab, d, int(np.floor(xc - np.sqrt(max(r * r - d * d, 0.0)))))
+                for lab, d in (("stagnation", 0), ("+r/2", int(round(r / 2))), ("-r/2", -int(round(r / 2))),
+                               ("+r", int(round(r))), ("-r", -int(round(r))))]
         return x0, [(lab, ny // 2 + d, nz // 2, xe) for lab, d, xe in offs]
     return None, []
 

@@ -43,6 +43,7 @@ def test_version_and_velocity_order_match_oracle(L, orc):
 def test_parameter_validation_without_device(L):
     good = lbm.make_params((16, 8, 1), tau=0.6)
     assert lbm.lbm_required_bytes(good) > 0
+    assert lbm.lbm_required_bytes(lbm.make_params((16, 8, 1), tau=0.6, root_finder="secant")) > 0
     bad = [
         lbm.make_params((0, 8, 1), tau=0.6),
         lbm.make_params((16, 8, 1), tau=0.4),
@@ -52,6 +53,8 @@ def test_parameter_validation_without_device(L):
         lbm.make_params((16, 8, 1), tau=0.0),                              # no tau and no Reynolds
         lbm.make_params((16, 8, 1), tau=0.6, storage=7),
         lbm.make_params((16, 8, 1), tau=0.6, mach=0.5, u_dir=(0, 0, 0)),
+        lbm.make_params((16, 8, 1), tau=0.6, root_finder=2),               # no such root finder
+        lbm.make_params((16, 8, 1), tau=0.6, root_finder="secant", storage="fp32s"),  # secant is FP64 only
     ]
     for p in bad:
         with pytest.raises(lbm.LbmError) as e:

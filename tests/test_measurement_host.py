@@ -62,3 +62,19 @@ def test_serving_side_summary(tmp_path):
     assert abs(r["busy_any_s"] - 5000e-9) < 1e-18
     assert r["other_kernels"] == 2
     assert abs(r["gap_p50_us"] - 4.0) < 1e-12  # gaps 0 and 4000 ns
+
+
+def test_serving_spread_over_seeds():
+    """Min, mean and max of each side's figures over trace seeds, and the
+    pool's gain (one-at-a-time over pool for latencies, pool over
+    one-at-a-time for throughput)."""
+    runs = [{"batched": {"p50_s": 1.0, "p99_s": 10.0, "aggregate_glups": 3.6},
+             "one_at_a_time": {"p50_s": 2.0, "p99_s": 11.0, "aggregate_glups": 3.5}},
+            {"batched": {"p50_s": 0.5, "p99_s": 12.0, "aggregate_glups": 3.4},
+             "one_at_a_time": {"p50_s": 2.0, "p99_s": 12.0, "aggregate_glups": 3.4}}]
+    s = bench.serving_spread(runs)
+    assert s["batched.p50_s"] == {"min": 0.5, "mean": 0.75, "max": 1.0}
+    assert s["one_at_a_time.aggregate_glups"]["max"] == 3.5
+    assert s["gain.p50_s"] == {"min": 2.0, "mean": 3.0, "max": 4.0}
+    assert abs(s["gain.p99_s"]["min"] - 1.0) < 1e-12 and abs(s["gain.p99_s"]["max"] - 1.1) < 1e-12
+    assert abs(s["gain.aggregate_glups"]["mean"] - (3.6 / 3.5 + 1.0) / 2) < 1e-12
