@@ -42,8 +42,9 @@ COPY_REPS = 5
 
 
 def _mode_of(name: str):
-    """Storage mode of a timed step kernel (the variant without statistics)."""
-    if "<true>" in name or "ILb1E" in name:
+    """Storage mode of a timed step kernel (the variant without statistics,
+    with the Newton root finder)."""
+    if "<true" in name or "ILb1E" in name or ", 1>" in name or "Li1EE" in name:
         return None
     for m, frags in STEP_KERNELS.items():
         if any(f in name for f in frags):
