@@ -73,3 +73,37 @@ def test_precision_study_mode_strings():
     for bad in ("fp8", "fp32s@rest", "fp64@stream"):
         with pytest.raises(ValueError):
             ps.parse_mode(bad)
+
+
+def test_bow_shock_position_on_a_row():
+    """The shock's mid-point on a synthetic density row: free stream 1 up to
+    x = 40, a linear rise to 2.2 over x = 40..44 and a plateau; the half
+    level 1.6 is crossed at x = 42, interpolated between cells."""
+    shape = (128, 5, 1)
+    rho = np.ones(shape[::-1])
+    x = np.arange(shape[0])
+    row = np.clip(1.0 + 0.3 * (x - 40), 1.0, 2.2)
+    rho[0, 2, :] = row
+    assert abs(precision_study.shock_front(rho, shape, 100, 2) - 42.0) < 1e-12
+    # no rise, or a row whose maximum is within 1% of the free stream: none
+    assert np.isnan(precision_study.shock_front(rho, shape, 100, 0))
+    rho[0, 1, 50:] = 1.005
+    assert np.isnan(precision_study.shock_front(rho, shape, 100, 1))
+
+
+def test_shock_rows_stop_at_the_body():
+    """The rows scanned for the bow shock end at the body: the airfoil's
+    stagnation row at its leading edge (the domain centre), the sphere's rows
+    where they meet the sphere."""
+    x0, rows = precision_study.front_rows("airfoil", (2048, 1024, 1), 1.0)
+    assert x0 == 1024 and rows[0] == ("stagnation", 512, 0, 1024)
+    _, solid, _ = precision_study.airfoil_case(1.0)
+    sm = solid.reshape(1, 1024, 2048)
+    for _, y, z, xe in rows:
+        assert not sm[z, y, :xe].any()
+    shape = (128, 64, 64)
+    x0, rows = precision_study.front_rows("sphere", shape, 0.25)
+    _, ssolid, _ = precision_study.sphere_case(0.25)
+    sm = ssolid.reshape(64, 64, 128)
+    for _, y, z, xe in rows:
+        assert not sm[z, y, :xe].any() and xe > 0
