@@ -452,22 +452,27 @@ def test_supersonic_airfoil_stays_stable(lbm, storage):
     s.close()
 
 
+@pytest.mark.timeout(600)
 def test_supersonic_airfoil_time_average_against_fp64(lbm):
-    """The supersonic airfoil comparison of FP32 storage with FP64, at half
-    size (1024 x 512, chord 128, Ma 1.5, Re 1e4; 6000 steps, the last 2000
-    averaged every 50).  The unsteady wake amplifies any last-bit change, so
-    FP32 is set beside the floor of FP64's own rounding: an FP64 run whose
-    Newton stops at 1e-13 instead of 1e-12.  Held: the time-averaged rho,
-    u, T and Mach number of FP32 (rest and stream shift) within ten times
-    that floor's difference; the bow shock on the stagnation row and a
-    quarter chord off it within 0.05 cells of FP64's; the shares of the
-    alpha branches 2 and 3 (alpha = 1.35, 1/tau) within 0.5 percentage
-    points of FP64's."""
+    """The supersonic airfoil comparison of FP32 storage with FP64 at full
+    size (2048 x 1024, chord 256, Ma 1.5, Re 1e4; 20,000 steps, the last
+    5000 averaged every 50; about a minute and a half).  The unsteady wake
+    amplifies any last-bit change, so FP32 is set beside the floor of FP64's
+    own rounding: an FP64 run whose Newton stops at 1e-13 instead of 1e-12.
+    Held: the time-averaged rho, u, T and Mach number of FP32 (rest and
+    stream shift) within ten times that floor's difference; the bow shock on
+    the stagnation row and an eighth and a quarter chord off it within 0.05
+    cells of FP64's; the shares of the alpha branches 2 and 3 (alpha = 1.35
+    and 1/tau) within 0.5 percentage points of FP64's.  (Branches 0 and 1
+    are not held: FP32's free-stream sensor sits near 0.008, the level its
+    1e-5 Newton stop leaves, and moves cells across eps = 0.01.)  At half
+    size the flow is less resolved, more cells sit near eps = 0.1, and that
+    floor moves a few per cent of them across it as well."""
     from paper_1910_13515_amd import precision_study as ps
-    res = ps.study("airfoil", steps=6000, scale=0.5, modes=["fp64", "fp64:1e-13", "fp32s", "fp32s@stream"],
-                   average=2000, sample=50)
+    res = ps.study("airfoil", steps=20000, scale=1.0, modes=["fp64", "fp64:1e-13", "fp32s", "fp32s@stream"],
+                   average=5000, sample=50)
     floor = res["modes"]["fp64:1e-13"]["vs_fp64"]
-    _log(f"half-size airfoil floor (FP64 1e-13 vs 1e-12): rho {floor['l2_rho']:.2e} u {floor['l2_u']:.2e} "
+    _log(f"airfoil floor (FP64 1e-13 vs 1e-12): rho {floor['l2_rho']:.2e} u {floor['l2_u']:.2e} "
          f"T {floor['l2_T']:.2e} Ma {floor['l2_mach']:.2e}; stand-off {res['modes']['fp64']['standoff']:.3f} cells")
     for m in ("fp32s", "fp32s@stream"):
         r = res["modes"][m]
@@ -475,9 +480,9 @@ def test_supersonic_airfoil_time_average_against_fp64(lbm):
         _log(f"{m}: rho {e['l2_rho']:.2e} u {e['l2_u']:.2e} T {e['l2_T']:.2e} Ma {e['l2_mach']:.2e}; shock shifts "
              f"{ {k: round(v, 4) for k, v in e['shock_x_shift'].items()} }; alpha share differences "
              f"{[round(100 * v, 3) for v in e['alpha_share_diff']]} pp")
-        assert r["finite"] and r["newton_failures"] < 1e-4 * 6000 * 1024 * 512
+        assert r["finite"] and r["newton_failures"] < 1e-4 * 20000 * 2048 * 1024
         for q in ("rho", "u", "T", "mach"):
             assert e[f"l2_{q}"] <= 10.0 * floor[f"l2_{q}"], q
-        for row in ("stagnation", "+c/4", "-c/4"):
+        for row in ("stagnation", "+c/8", "-c/8", "+c/4", "-c/4"):
             assert abs(e["shock_x_shift"][row]) <= 0.05, row
         assert abs(e["alpha_share_diff"][2]) <= 0.005 and abs(e["alpha_share_diff"][3]) <= 0.005

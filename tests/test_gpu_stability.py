@@ -1,5 +1,5 @@
 """Stability of plain BGK against BGK with the Knudsen-number-based relaxation
-on the supersonic NACA0012 flow (Sec. 4), held as verdicts.
+on the supersonic NACA0012 flow (Sec. 4), held as stable or unstable outcomes.
 
 Sec. 4 states three things about this flow:
   * plain BGK with the equilibrium of Eq. (eq:discrete-equilibrium) is stable
