@@ -80,7 +80,9 @@ typedef enum {
 /* Problem statement.  Every field is read during lbm_create() only; the
  * pointers may be freed afterwards.  Zero/NULL selects the default noted. */
 typedef struct {
-    int32_t nx, ny, nz;        /* cells (>= 1; a non-periodic axis needs >= 7) */
+    int32_t nx, ny, nz;        /* cells (>= 1; a non-periodic axis needs >= 7); nx*ny*nz < 2^28 in FP64,
+                                  2^29 in FP32, 2^30 in FP16 (the gathers' 32-bit offsets), and the
+                                  footprint of lbm_required_bytes must fit the arena */
     int32_t storage;           /* lbm_storage */
     int32_t shift_ref;         /* shifted storage only: 0 = rest-state equilibrium at (rho_ref, T_ref),
                                   1 = equilibrium of the reference stream (rho_ref, u_ref, T_ref); with 1

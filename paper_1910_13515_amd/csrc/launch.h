@@ -10,9 +10,13 @@
 
 namespace lbm13 {
 
-// solver: 0 Newton-Raphson, 1 the secant variant (FP64 storage only)
+// solver: 0 Newton-Raphson, 1 the secant variant (FP64 storage only);
+// wide: a reduced-precision slot of kWideCells cells or more (row stores from
+// 64-bit lane addresses)
+constexpr int64_t kWideCells = (int64_t)1 << 28;
 hipError_t launch_step(int storage, const SlotTable *tab, int grid, int j, int64_t *stats, hipStream_t st,
-                       int solver = 0);
+                       int solver = 0, bool wide = false);
+// the kernel the pool's graph launches (Newton, slots below kWideCells cells)
 const void *step_kernel_symbol(int storage);
 hipError_t launch_diag(int storage, const SlotTable *tab, int grid, int j, double *diag, hipStream_t st);
 hipError_t launch_init(int storage, const SlotDesc &d, const double *fields, unsigned long long *failed,

@@ -75,12 +75,10 @@ std::string validate(const lbm_params *p)
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return "grid dimensions must be >= 1";
     const int64_t n = (int64_t)p->nx * p->ny * p->nz;
     if (p->storage < LBM_STORE_FP64 || p->storage > LBM_STORE_FP16_SHIFTED) return "unknown storage mode";
-    // the kernels address two population arrays from one base with 32-bit byte offsets
+    // the gathers address two population arrays (a velocity pair) from one
+    // base with 32-bit byte offsets: n < 2^28 in FP64, 2^29 in FP32, 2^30 in
+    // FP16 (the row stores switch to 64-bit lane addresses above 2^28 cells)
     if (2 * n * storage_bytes(p->storage) >= ((int64_t)1 << 32)) return "grid too large for this storage mode";
-    // FP32: row stores address four population arrays from one base
-    if (p->storage == LBM_STORE_FP32_SHIFTED && 4 * n * 4 >= ((int64_t)1 << 32)) return "grid too large for FP32 storage";
-    // the FP16 row stores reach 8 planes (of 2n bytes) from one 32-bit lane offset
-    if (p->storage == LBM_STORE_FP16_SHIFTED && 8 * n * 2 >= ((int64_t)1 << 32)) return "grid too large for FP16 storage";
     if (p->shift_ref < 0 || p->shift_ref > 1) return "shift_ref must be 0 or 1";
     const int dims[3] = {p->nx, p->ny, p->nz};
     for (int a = 0; a < 3; ++a) {
@@ -600,7 +598,7 @@ int lbm_step(lbm_ctx *c, int32_t nsteps, lbm_step_stats *stats)
         const int j = (int)((c->steps + s) & 1);
         // statistics only when asked for: the kernels without them run lighter
         HIP_TRY(c, launch_step(c->storage, c->d_table, c->grid, j, stats ? d_stats : nullptr, c->stream,
-                               c->params.root_finder));
+                               c->params.root_finder, c->desc.n >= kWideCells));
     }
     c->steps += nsteps;
     if (!stats) return LBM_OK;
@@ -1031,6 +1029,8 @@ int lbm_pool_admit(lbm_pool *p, const lbm_params *params, int32_t nsteps, int32_
     if (!params || !slot_out || nsteps < 0) return pool_fail(p, LBM_E_INVAL, "invalid argument");
     if (params->storage != p->storage) return pool_fail(p, LBM_E_INVAL, "storage differs from the pool's");
     if (params->root_finder != 0) return pool_fail(p, LBM_E_INVAL, "the pool runs the Newton root finder only");
+    if ((int64_t)params->nx * params->ny * params->nz >= kWideCells)
+        return pool_fail(p, LBM_E_INVAL, "pool slots take fewer than 2^28 cells");
     const int64_t need = lbm_required_bytes(params);
     if (need < 0) return pool_fail(p, (int)need, lbm_last_error(nullptr));
     int slot = -1;

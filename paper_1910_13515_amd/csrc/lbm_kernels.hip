@@ -593,6 +593,9 @@ __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const 
 
 }  // namespace f32
 
+// kWide: grids of 2^28 cells or more, whose row stores take 64-bit lane
+// addresses (a separate instantiation keeps the common case's registers)
+template <bool kWide>
 __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f32(const SlotTable *__restrict__ tab, int j,
                                                                    int64_t *__restrict__ stats)
 {
@@ -651,9 +654,10 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f32(const SlotTa
         __builtin_amdgcn_s_setprio(1);
         const uint64_t nS64 = (uint64_t)d.n * 4;
         const float *col = park + wave * kSegment;
-        if (full) {
+        if (full && !kWide) {
             // lanes 16r..16r+15 store row i0 + r, 4 cells each: one uniform
-            // base per group of 4 rows and one 32-bit lane offset
+            // base per group of 4 rows and one 32-bit lane offset (4 planes
+            // of 4n bytes stay below 2^32 for n < 2^28)
             const int r = lane >> 4, c4 = (lane & 15) * 4;
             uint32_t voff = (uint32_t)r * (uint32_t)nS64 + (cell0 + (uint32_t)c4) * 4u;
             const float *lcol = col + r * kBlockThreads + c4;
@@ -666,6 +670,19 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f32(const SlotTa
                     // the caches have turned over
                     __builtin_nontemporal_store(
                         v, reinterpret_cast<f32::v4f __attribute__((address_space(1))) *>(dstb + (uint64_t)i0 * nS64 + voff));
+                }
+            }
+        } else if (full) {
+            // 2^28 cells or more: the same stores from a 64-bit lane address
+            const int r = lane >> 4, c4 = (lane & 15) * 4;
+            gbyte *lane_base = dstb + (uint64_t)r * nS64 + (uint64_t)(cell0 + (uint32_t)c4) * 4u;
+            const float *lcol = col + r * kBlockThreads + c4;
+#pragma unroll
+            for (int i0 = 0; i0 < 2 * kQ; i0 += 4) {
+                if (i0 + r < 2 * kQ) {
+                    const f32::v4f v = *reinterpret_cast<const f32::v4f *>(lcol + i0 * kBlockThreads);
+                    __builtin_nontemporal_store(
+                        v, reinterpret_cast<f32::v4f __attribute__((address_space(1))) *>(lane_base + (uint64_t)i0 * nS64));
                 }
             }
         } else if (in_grid) {
@@ -691,7 +708,7 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f32(const SlotTa
 // arithmetic through the decoding park, results encoded back into the row
 // words, and full rows leaving as 16-byte-per-lane stores of eight cells
 // (eight rows per instruction).
-template <bool kStats>
+template <bool kStats, bool kWide>
 __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f16(const SlotTable *__restrict__ tab, int j,
                                                                    int64_t *__restrict__ stats)
 {
@@ -751,8 +768,11 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f16(const SlotTa
         __builtin_amdgcn_s_setprio(1);
         const uint64_t nS64 = (uint64_t)d.n * 2;
         const uint32_t *col = park + wave * kSegment;
-        if (full) {
-            // lanes 8r..8r+7 store row i0 + r, eight cells each
+        typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+        if (full && !kWide) {
+            // lanes 8r..8r+7 store row i0 + r, eight cells each: one uniform
+            // base per group of 8 rows and one 32-bit lane offset (8 planes
+            // of 2n bytes stay below 2^32 for n < 2^28)
             const int r = lane >> 3, c8 = (lane & 7) * 8;
             uint32_t voff = (uint32_t)r * (uint32_t)nS64 + (cell0 + (uint32_t)c8) * 2u;
             const uint32_t *lcol = col + r * kBlockThreads + c8;
@@ -760,7 +780,6 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f16(const SlotTa
 #pragma unroll
             for (int i0 = 0; i0 < 2 * kQ; i0 += 8) {
                 if (i0 + r < 2 * kQ) {
-                    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
                     const v4u w0 = *reinterpret_cast<const v4u *>(lcol + i0 * kBlockThreads);
                     const v4u w1 = *reinterpret_cast<const v4u *>(lcol + i0 * kBlockThreads + 4);
                     // every word holds a half zero-extended (the gather's
@@ -769,6 +788,22 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f16(const SlotTa
                                    w1.z | (w1.w << 16)};
                     __builtin_nontemporal_store(
                         v, reinterpret_cast<v4u __attribute__((address_space(1))) *>(dstb + (uint64_t)i0 * nS64 + voff));
+                }
+            }
+        } else if (full) {
+            // 2^28 cells or more: the same stores from a 64-bit lane address
+            const int r = lane >> 3, c8 = (lane & 7) * 8;
+            gbyte *lane_base = dstb + (uint64_t)r * nS64 + (uint64_t)(cell0 + (uint32_t)c8) * 2u;
+            const uint32_t *lcol = col + r * kBlockThreads + c8;
+#pragma unroll
+            for (int i0 = 0; i0 < 2 * kQ; i0 += 8) {
+                if (i0 + r < 2 * kQ) {
+                    const v4u w0 = *reinterpret_cast<const v4u *>(lcol + i0 * kBlockThreads);
+                    const v4u w1 = *reinterpret_cast<const v4u *>(lcol + i0 * kBlockThreads + 4);
+                    const v4u v = {w0.x | (w0.y << 16), w0.z | (w0.w << 16), w1.x | (w1.y << 16),
+                                   w1.z | (w1.w << 16)};
+                    __builtin_nontemporal_store(
+                        v, reinterpret_cast<v4u __attribute__((address_space(1))) *>(lane_base + (uint64_t)i0 * nS64));
                 }
             }
         } else if (in_grid) {
@@ -1337,29 +1372,33 @@ hipError_t launch_diag(int storage, const SlotTable *tab, int grid, int j, doubl
 }
 
 hipError_t launch_step(int storage, const SlotTable *tab, int grid, int j, int64_t *stats, hipStream_t st,
-                       int solver)
+                       int solver, bool wide)
 {
+    const dim3 g(grid), b(kBlockThreads);
     switch (storage) {
     case kStoreF64:
         if (solver == 1) {
-            if (stats)
-                hipLaunchKernelGGL((step_kernel_f64<true, 1>), dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
-            else
-                hipLaunchKernelGGL((step_kernel_f64<false, 1>), dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
+            if (stats) hipLaunchKernelGGL((step_kernel_f64<true, 1>), g, b, 0, st, tab, j, stats);
+            else hipLaunchKernelGGL((step_kernel_f64<false, 1>), g, b, 0, st, tab, j, stats);
         } else if (stats) {
-            hipLaunchKernelGGL((step_kernel_f64<true, 0>), dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
+            hipLaunchKernelGGL((step_kernel_f64<true, 0>), g, b, 0, st, tab, j, stats);
         } else {
-            hipLaunchKernelGGL((step_kernel_f64<false, 0>), dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
+            hipLaunchKernelGGL((step_kernel_f64<false, 0>), g, b, 0, st, tab, j, stats);
         }
         break;
     case kStoreF32:
-        hipLaunchKernelGGL(step_kernel_f32, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
+        if (wide) hipLaunchKernelGGL((step_kernel_f32<true>), g, b, 0, st, tab, j, stats);
+        else hipLaunchKernelGGL((step_kernel_f32<false>), g, b, 0, st, tab, j, stats);
         break;
     default:
-        if (stats)
-            hipLaunchKernelGGL(step_kernel_f16<true>, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
-        else
-            hipLaunchKernelGGL(step_kernel_f16<false>, dim3(grid), dim3(kBlockThreads), 0, st, tab, j, stats);
+        if (wide) {
+            if (stats) hipLaunchKernelGGL((step_kernel_f16<true, true>), g, b, 0, st, tab, j, stats);
+            else hipLaunchKernelGGL((step_kernel_f16<false, true>), g, b, 0, st, tab, j, stats);
+        } else if (stats) {
+            hipLaunchKernelGGL((step_kernel_f16<true, false>), g, b, 0, st, tab, j, stats);
+        } else {
+            hipLaunchKernelGGL((step_kernel_f16<false, false>), g, b, 0, st, tab, j, stats);
+        }
         break;
     }
     return hipGetLastError();
@@ -1369,8 +1408,8 @@ const void *step_kernel_symbol(int storage)
 {
     switch (storage) {
     case kStoreF64: return reinterpret_cast<const void *>(&step_kernel_f64<false, 0>);
-    case kStoreF32: return reinterpret_cast<const void *>(&step_kernel_f32);
-    default: return reinterpret_cast<const void *>(&step_kernel_f16<false>);
+    case kStoreF32: return reinterpret_cast<const void *>(&step_kernel_f32<false>);
+    default: return reinterpret_cast<const void *>(&step_kernel_f16<false, false>);
     }
 }
 

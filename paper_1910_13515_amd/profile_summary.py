@@ -42,9 +42,10 @@ COPY_REPS = 5
 
 
 def _mode_of(name: str):
-    """Storage mode of a timed step kernel (the variant without statistics,
-    with the Newton root finder)."""
-    if "<true" in name or "ILb1E" in name or ", 1>" in name or "Li1EE" in name:
+    """Storage mode of a timed step kernel: the variant without statistics,
+    with the Newton root finder, for grids below 2^28 cells (every template
+    flag false or 0)."""
+    if "true" in name or "Lb1E" in name or ", 1>" in name or "Li1EE" in name:
         return None
     for m, frags in STEP_KERNELS.items():
         if any(f in name for f in frags):
