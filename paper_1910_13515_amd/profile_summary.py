@@ -168,7 +168,7 @@ def summarize(root, commands=None):
                 if c in sq[m]:
                     v[c.lower()] = sq[m][c]
     # where the waves' resident cycles go (optional second run): the share
-    # spent issuing VALU and LDS instructions and waiting on a dependency
+    # spent issuing VALU and LDS instructions and waiting to issue
     sq2 = sq_counters(root, "pmc_sq2")
     for m, v in modes.items():
         w = sq2.get(m, {}).get("SQ_WAVE_CYCLES")
@@ -214,9 +214,9 @@ def summarize(root, commands=None):
                              f"{v['avg_ns'] / 1e3:.0f} | {v['valu_issue_frac']:.2f} |")
     if any("wave_cycles" in v for v in modes.values()):
         lines += ["", "Where a wave's resident cycles go (rocprofv3 SQ_ACTIVE_INST_VALU, SQ_ACTIVE_INST_LDS, "
-                  "SQ_WAIT_INST_ANY over SQ_WAVE_CYCLES, summed over the dispatch's waves), with the waves resident "
+                  "SQ_WAIT_INST_ANY over SQ_WAVE_CYCLES, summed over the dispatch's waves; all in the same quad-cycle units), with the waves resident "
                   "per SIMD (SQ_WAVES per dispatch over the 1024 SIMDs, per pass of the persistent grid):", "",
-                  "| storage | waves per dispatch | VALU-issuing share | LDS-issuing share | waiting on a dependency | "
+                  "| storage | waves per dispatch | VALU-issuing share | LDS-issuing share | waiting to issue | "
                   "LDS bank conflicts |", "|---|---|---|---|---|---|"]
         for m, v in modes.items():
             if "wave_cycles" in v:
