@@ -302,7 +302,9 @@ int lbm_pool_create(int32_t storage, int32_t max_slots, int32_t graph_steps, int
  * creates it in place on the admission stream (initial state written, as
  * lbm_create) and returns its slot index.  Allowed while a round is in flight.
  * LBM_E_NOMEM when no slot or no free range fits (nothing is changed); other
- * errors as lbm_create.  A slot admitted with nsteps = 0 never runs. */
+ * errors as lbm_create.  A slot admitted with nsteps = 0 never runs.  The
+ * pool's graph runs one kernel for all slots: LBM_E_INVAL for
+ * params->root_finder != 0 and for grids of 2^28 cells or more. */
 int lbm_pool_admit(lbm_pool *pool, const lbm_params *params, int32_t nsteps, int32_t *slot_out);
 
 /* Starts a round without waiting: picks the slots (policy), uploads the slot
