@@ -34,6 +34,9 @@ struct StoreTraits<double> {
     static constexpr bool kShift = false;
     static constexpr bool kScale = false;
     static constexpr int kWavesPerSimd = 1;  // FP64 arithmetic needs the full register file
+    // f_i and g_i of a cell side by side: one 16-byte record per cell and
+    // velocity, so that one 16-byte transfer per lane moves both
+    static constexpr bool kPaired = true;
 };
 
 // Global-memory pointers (address space 1): loads and stores then use a
@@ -43,6 +46,11 @@ using gcbyte = const char __attribute__((address_space(1)));
 
 template <class S>
 __device__ __forceinline__ S gload(gcbyte *base, uint32_t off)
+{
+    return *reinterpret_cast<const S __attribute__((address_space(1))) *>(base + off);
+}
+template <class S>
+__device__ __forceinline__ S gload64(gcbyte *base, uint64_t off)
 {
     return *reinterpret_cast<const S __attribute__((address_space(1))) *>(base + off);
 }
@@ -75,6 +83,7 @@ struct StoreTraits<float> {
     static constexpr bool kShift = true;
     static constexpr bool kScale = false;
     static constexpr int kWavesPerSimd = 2;  // 256 registers per lane, LDS for the parked populations
+    static constexpr bool kPaired = false;   // one plane per population
 };
 template <>
 struct StoreTraits<_Float16> {
@@ -82,7 +91,33 @@ struct StoreTraits<_Float16> {
     static constexpr bool kShift = true;
     static constexpr bool kScale = true;  // deviations stored divided by a power of two per shell
     static constexpr int kWavesPerSimd = 2;
+    static constexpr bool kPaired = false;
 };
+
+// Where population pop (0..38 f, 39..77 g) of a cell sits in a population
+// buffer of n cells: paired storage keeps [39][n][2] (f_i, g_i), the other
+// modes [78][n].
+template <class S>
+__device__ __forceinline__ int64_t pidx(int pop, int64_t cell, int64_t n)
+{
+    if constexpr (StoreTraits<S>::kPaired) return (int64_t)(pop % kQ) * 2 * n + 2 * cell + (pop >= kQ ? 1 : 0);
+    else return (int64_t)pop * n + cell;
+}
+// bytes per cell in one velocity's plane, and byte offsets of the f and g
+// planes of velocity i from the buffer base
+template <class S>
+constexpr uint32_t kCellBytes = StoreTraits<S>::kPaired ? 2 * sizeof(S) : sizeof(S);
+template <class S>
+__device__ __forceinline__ uint64_t fplane(int i, int64_t n)
+{
+    return (uint64_t)i * (uint64_t)n * kCellBytes<S>;
+}
+template <class S>
+__device__ __forceinline__ uint64_t gplane(int i, int64_t n)
+{
+    if constexpr (StoreTraits<S>::kPaired) return fplane<S>(i, n) + sizeof(S);
+    else return fplane<S>(kQ + i, n);
+}
 
 // Coordinate of the pull source along one axis, for a cell at coordinate v
 // and velocity component c: periodic axes wrap; Neumann faces read the
@@ -118,12 +153,6 @@ __device__ __forceinline__ bool is_fluid_coord(const SlotDesc &d, int x, int y, 
     return f;
 }
 
-template <class S, class C>
-__device__ __forceinline__ C load_pop(const S *buf, int64_t n, int pop, int64_t idx)
-{
-    return static_cast<C>(buf[(int64_t)pop * n + idx]);
-}
-
 // wave-level integer reductions (64 lanes)
 __device__ __forceinline__ int32_t wave_sum(int32_t v)
 {
@@ -142,27 +171,27 @@ __device__ __forceinline__ int32_t wave_max(int32_t v)
 }
 
 // Gather of one opposite pair p (velocities a = 2p+1 with c_p and b = 2p+2
-// with -c_p) into a fluid cell.  Both populations are addressed from the base
-// of array a, so that a half-way bounce-back (which reads the cell's own
-// opposite population) stays a 32-bit offset from the same uniform base:
-//   f_a: from x - c_p, or when blocked f_b at the cell  (offset n + cell)
+// with -c_p) into a fluid cell, for read-outs (register loads).  Both
+// populations are addressed from the planes of velocity a, so that a half-way
+// bounce-back (which reads the cell's own opposite population) is an offset
+// from the same base; nP is the byte distance from plane a to plane b:
+//   f_a: from x - c_p, or when blocked f_b at the cell  (offset nP + cell)
 //   f_b: from x + c_p, or when blocked f_a at the cell  (offset cell)
 template <int P, class S, class C>
-__device__ __forceinline__ void gather_pair(const SlotDesc &d, gcbyte *srcb, uint64_t nS64, uint32_t nS,
-                                            uint32_t cellS, uint64_t links, const uint32_t (&Xo)[7],
-                                            const uint32_t (&Yo)[7], const uint32_t (&Zo)[7], const Park<C> &pk,
-                                            MomentAcc<C> &acc)
+__device__ __forceinline__ void gather_pair(const SlotDesc &d, gcbyte *srcb, uint64_t nP, uint32_t cellS,
+                                            uint64_t links, const uint32_t (&Xo)[7], const uint32_t (&Yo)[7],
+                                            const uint32_t (&Zo)[7], const Park<C> &pk, MomentAcc<C> &acc)
 {
     constexpr int a = 2 * P + 1, b = 2 * P + 2;
     constexpr int cx = kPairVel[P][0], cy = kPairVel[P][1], cz = kPairVel[P][2];
-    uint32_t oa = Xo[cx + 3] + (Yo[cy + 3] + Zo[cz + 3]);
-    uint32_t ob = nS + (Xo[3 - cx] + (Yo[3 - cy] + Zo[3 - cz]));
-    oa = ((links >> a) & 1ull) ? nS + cellS : oa;
-    ob = ((links >> b) & 1ull) ? cellS : ob;
-    gcbyte *bf = srcb + (uint64_t)a * nS64;
-    gcbyte *bg = srcb + (uint64_t)(kQ + a) * nS64;
-    C fa = C(gload<S>(bf, oa)), fb = C(gload<S>(bf, ob));
-    C ga = C(gload<S>(bg, oa)), gb = C(gload<S>(bg, ob));
+    uint64_t oa = Xo[cx + 3] + (Yo[cy + 3] + Zo[cz + 3]);
+    uint64_t ob = nP + (Xo[3 - cx] + (Yo[3 - cy] + Zo[3 - cz]));
+    oa = ((links >> a) & 1ull) ? nP + cellS : oa;
+    ob = ((links >> b) & 1ull) ? (uint64_t)cellS : ob;
+    gcbyte *bf = srcb + fplane<S>(a, d.n);
+    gcbyte *bg = srcb + gplane<S>(a, d.n);
+    C fa = C(gload64<S>(bf, oa)), fb = C(gload64<S>(bf, ob));
+    C ga = C(gload64<S>(bg, oa)), gb = C(gload64<S>(bg, ob));
     if constexpr (StoreTraits<S>::kScale) {
         const C sf = C(d.shell_scale[0][shell(a)]), sg = C(d.shell_scale[1][shell(a)]);
         fa *= sf;
@@ -195,12 +224,12 @@ __device__ __forceinline__ void gather_pair(const SlotDesc &d, gcbyte *srcb, uin
 }
 
 template <class S, class C, int... P>
-__device__ __forceinline__ void gather_pairs(const SlotDesc &d, gcbyte *srcb, uint64_t nS64, uint32_t nS,
-                                             uint32_t cellS, uint64_t links, const uint32_t (&Xo)[7],
-                                             const uint32_t (&Yo)[7], const uint32_t (&Zo)[7], const Park<C> &pk,
-                                             MomentAcc<C> &acc, std::integer_sequence<int, P...>)
+__device__ __forceinline__ void gather_pairs(const SlotDesc &d, gcbyte *srcb, uint64_t nP, uint32_t cellS,
+                                             uint64_t links, const uint32_t (&Xo)[7], const uint32_t (&Yo)[7],
+                                             const uint32_t (&Zo)[7], const Park<C> &pk, MomentAcc<C> &acc,
+                                             std::integer_sequence<int, P...>)
 {
-    (gather_pair<P, S, C>(d, srcb, nS64, nS, cellS, links, Xo, Yo, Zo, pk, acc), ...);
+    (gather_pair<P, S, C>(d, srcb, nP, cellS, links, Xo, Yo, Zo, pk, acc), ...);
 }
 
 template <int I, class S, class C, class PK>
@@ -241,21 +270,21 @@ __device__ __forceinline__ void diag_cell(const SlotDesc &d, const S *src, int x
         return;
     }
 
-    // byte offsets of the source coordinates x - c, c = -3..3, per axis
+    // byte offsets of the source coordinates x - c, c = -3..3, per axis,
+    // within one velocity's plane
+    constexpr uint32_t cb = kCellBytes<S>;
     const uint32_t nx = (uint32_t)d.nx, nxy = (uint32_t)d.nx * (uint32_t)d.ny;
     uint32_t Xo[7], Yo[7], Zo[7];
 #pragma unroll
     for (int c = -3; c <= 3; ++c) {
-        Xo[c + 3] = (uint32_t)source_coord(x, c, d.nx, d.axis[0] == kAxisPeriodic, d.neumann_lo[0], d.neumann_hi[0]) *
-                    (uint32_t)sizeof(S);
+        Xo[c + 3] = (uint32_t)source_coord(x, c, d.nx, d.axis[0] == kAxisPeriodic, d.neumann_lo[0], d.neumann_hi[0]) * cb;
         Yo[c + 3] = (uint32_t)source_coord(y, c, d.ny, d.axis[1] == kAxisPeriodic, d.neumann_lo[1], d.neumann_hi[1]) *
-                    nx * (uint32_t)sizeof(S);
+                    nx * cb;
         Zo[c + 3] = (uint32_t)source_coord(z, c, d.nz, d.axis[2] == kAxisPeriodic, d.neumann_lo[2], d.neumann_hi[2]) *
-                    nxy * (uint32_t)sizeof(S);
+                    nxy * cb;
     }
-    const uint64_t nS64 = (uint64_t)d.n * sizeof(S);
-    const uint32_t nS = (uint32_t)nS64;
-    const uint32_t cellS = cell * (uint32_t)sizeof(S);
+    const uint64_t nP = (uint64_t)d.n * cb;
+    const uint32_t cellS = cell * cb;
     gcbyte *srcb = (gcbyte *)src;
 
     // moments accumulate while the populations are parked (shifted storage
@@ -273,8 +302,8 @@ __device__ __forceinline__ void diag_cell(const SlotDesc &d, const S *src, int x
         macc.e = C(-0.0);
     }
     {
-        C f0v = C(gload<S>(srcb, cellS));
-        C g0v = C(gload<S>(srcb + (uint64_t)kQ * nS64, cellS));
+        C f0v = C(gload<S>(srcb + fplane<S>(0, d.n), cellS));
+        C g0v = C(gload<S>(srcb + gplane<S>(0, d.n), cellS));
         if constexpr (StoreTraits<S>::kScale) {
             f0v *= C(d.shell_scale[0][0]);
             g0v *= C(d.shell_scale[1][0]);
@@ -284,7 +313,7 @@ __device__ __forceinline__ void diag_cell(const SlotDesc &d, const S *src, int x
         macc.rho += f0v;
         macc.sg = g0v;
     }
-    gather_pairs<S, C>(d, srcb, nS64, nS, cellS, links, Xo, Yo, Zo, pk, macc, PairSeq{});
+    gather_pairs<S, C>(d, srcb, nP, cellS, links, Xo, Yo, Zo, pk, macc, PairSeq{});
     // keep the parked values out of registers across the solve
     __asm__ volatile("" ::: "memory");
     const C rho = macc.rho;
@@ -825,19 +854,18 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f16(const SlotTa
 }
 
 // ---------------------------------------------------------------------------
-// FP64 step with the same structure as the FP32 one: the gather goes global ->
-// LDS directly, each double as two dword transfers (low words of the 64 cells
-// of a row, then high words), so that no register holds a gathered value and
-// every transfer of the wave is in flight at once.  LDS row i of wave w: 64
-// low words at i*512 + w*128, 64 high words 64 words further; results go
-// back to the same places, and full rows leave as 16-byte-per-lane stores of
-// two cells.  One wave per SIMD (the FP64 solve needs the register file).
+// FP64 step.  Populations are stored paired, one 16-byte record (f_i, g_i)
+// per cell and velocity, so the gather moves a cell's f_i and g_i with one
+// 16-byte global -> LDS transfer per lane: 39 transfers of 1 KB per 64-cell
+// segment, all in flight together with the 13 multiplier loads (the vector
+// memory counter holds 63).  LDS row i of a wave holds the 64 records of
+// velocity i; results replace them and leave as one 16-byte store per lane
+// and velocity.  One wave per SIMD (the FP64 solve needs the register file).
 namespace f64 {
 
-using lds_u32 = uint32_t __attribute__((address_space(3)));
-typedef uint32_t v4u __attribute__((ext_vector_type(4)));
-typedef uint32_t v2u __attribute__((ext_vector_type(2)));
-constexpr int kRowWords = 2 * kBlockThreads;  // words per LDS row of the block
+typedef double v2d __attribute__((ext_vector_type(2)));
+using lds_v2d = v2d __attribute__((address_space(3)));
+constexpr uint32_t kRec = 16;  // bytes of one (f_i, g_i) record
 
 // a uniform plane base forced into SGPRs where it is used: the access is
 // then base + 32-bit lane offset, and no per-lane 64-bit address stays live
@@ -846,104 +874,118 @@ __device__ __forceinline__ gbyte *splane(gbyte *p)
     __asm__ volatile("" : "+s"(p));
     return p;
 }
-
-struct Park {
-    lds_u32 *base;  // lane's low word of row 0
-    __device__ __forceinline__ double get(int i) const
-    {
-        const uint32_t lo = base[i * kRowWords], hi = base[i * kRowWords + kSegment];
-        return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));
-    }
-    __device__ __forceinline__ void put(int i, double v) const
-    {
-        const uint64_t b = __builtin_bit_cast(uint64_t, v);
-        base[i * kRowWords] = (uint32_t)b;
-        base[i * kRowWords + kSegment] = (uint32_t)(b >> 32);
-    }
-};
-
 __device__ __forceinline__ gcbyte *splane(gcbyte *p)
 {
     __asm__ volatile("" : "+s"(p));
     return p;
 }
 
-// the two dword transfers of one double per lane into LDS row `row`: low
-// words from base + off, high words from (base + 4) + off, both a uniform
-// base plus the same 32-bit lane offset (no per-lane 64-bit address)
-__device__ __forceinline__ void dma8(gcbyte *base, uint32_t off, lds_u32 *row)
+struct Park {
+    lds_v2d *base;  // the lane's record in row 0 of its wave
+    __device__ __forceinline__ v2d get(int i) const { return base[i * kSegment]; }
+    __device__ __forceinline__ void put(int i, v2d v) const { base[i * kSegment] = v; }
+};
+
+// one 16-byte transfer per lane into LDS row `row` (the hardware places lane
+// l's record at row + 16 l): a uniform base plus a 32-bit lane offset, or a
+// per-lane address
+__device__ __forceinline__ void dma16(gcbyte *base, uint32_t off, lds_v2d *row)
 {
-    gcbyte *lo = splane(base);
-    gcbyte *hi = splane(base + 4);
-    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(lo + off),
-                                     (void __attribute__((address_space(3))) *)row, 4, 0, 0);
-    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(hi + off),
-                                     (void __attribute__((address_space(3))) *)(row + kSegment), 4, 0, 0);
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(splane(base) + off),
+                                     (void __attribute__((address_space(3))) *)row, 16, 0, 0);
+}
+__device__ __forceinline__ void dma16_at(gcbyte *addr, lds_v2d *row)
+{
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)addr,
+                                     (void __attribute__((address_space(3))) *)row, 16, 0, 0);
 }
 
-// byte offsets of the pull sources x - c, c = -3..3, along each axis
+// byte offsets of the pull sources x - c, c = -3..3, along each axis, within
+// one velocity's plane of records
 __device__ __forceinline__ void source_offsets(const SlotDesc &d, int x, int y, int z, uint32_t (&Xo)[7],
                                                uint32_t (&Yo)[7], uint32_t (&Zo)[7])
 {
     const uint32_t nx = (uint32_t)d.nx, nxy = (uint32_t)d.nx * (uint32_t)d.ny;
 #pragma unroll
     for (int c = -3; c <= 3; ++c) {
-        Xo[c + 3] = (uint32_t)source_coord(x, c, d.nx, d.axis[0] == kAxisPeriodic, d.neumann_lo[0], d.neumann_hi[0]) * 8u;
-        Yo[c + 3] = (uint32_t)source_coord(y, c, d.ny, d.axis[1] == kAxisPeriodic, d.neumann_lo[1], d.neumann_hi[1]) * nx * 8u;
-        Zo[c + 3] = (uint32_t)source_coord(z, c, d.nz, d.axis[2] == kAxisPeriodic, d.neumann_lo[2], d.neumann_hi[2]) * nxy * 8u;
+        Xo[c + 3] = (uint32_t)source_coord(x, c, d.nx, d.axis[0] == kAxisPeriodic, d.neumann_lo[0], d.neumann_hi[0]) * kRec;
+        Yo[c + 3] = (uint32_t)source_coord(y, c, d.ny, d.axis[1] == kAxisPeriodic, d.neumann_lo[1], d.neumann_hi[1]) * nx * kRec;
+        Zo[c + 3] = (uint32_t)source_coord(z, c, d.nz, d.axis[2] == kAxisPeriodic, d.neumann_lo[2], d.neumann_hi[2]) * nxy * kRec;
     }
 }
 
-// gather of one cell's 78 values (rows: the wave's low words of row 0);
-// copy = the cell's own values
+// gather of one cell's 39 records (rows: row 0 of the wave).  copy: the
+// cell's own records.  A blocked link (half-way bounce-back) reads the
+// opposite velocity's record at the cell itself, in another plane: waves
+// with such a link (linked, uniform) take per-lane addresses, the others a
+// uniform plane base plus a 32-bit offset.
 __device__ __forceinline__ void gather(const SlotDesc &d, gcbyte *srcb, int x, int y, int z, uint32_t cell,
-                                       uint64_t links, bool copy, lds_u32 *rows)
+                                       uint64_t links, bool copy, bool linked, lds_v2d *rows)
 {
-    const uint64_t nS64 = (uint64_t)d.n * 8;
-    const uint32_t nS = (uint32_t)nS64;
-    const uint32_t cellS = cell * 8u;
+    const uint64_t nP = (uint64_t)d.n * kRec;
+    const uint32_t cellR = cell * kRec;
     uint32_t Xo[7], Yo[7], Zo[7];
     source_offsets(d, x, y, z, Xo, Yo, Zo);
-    dma8(srcb, cellS, rows);
-    dma8(srcb + (uint64_t)kQ * nS64, cellS, rows + kQ * kRowWords);
+    dma16(srcb, cellR, rows);
+    if (!linked) {
 #pragma unroll
-    for (int p = 0; p < kPairs; ++p) {
-        const int a = 2 * p + 1, b = 2 * p + 2;
-        const int cx = kPairVel[p][0], cy = kPairVel[p][1], cz = kPairVel[p][2];
-        uint32_t oa = Xo[cx + 3] + (Yo[cy + 3] + Zo[cz + 3]);
-        uint32_t ob = nS + (Xo[3 - cx] + (Yo[3 - cy] + Zo[3 - cz]));
-        oa = ((links >> a) & 1ull) ? nS + cellS : oa;
-        ob = ((links >> b) & 1ull) ? cellS : ob;
-        oa = copy ? cellS : oa;
-        ob = copy ? nS + cellS : ob;
-        gcbyte *bf = srcb + (uint64_t)a * nS64;
-        gcbyte *bg = srcb + (uint64_t)(kQ + a) * nS64;
-        dma8(bf, oa, rows + a * kRowWords);
-        dma8(bf, ob, rows + b * kRowWords);
-        dma8(bg, oa, rows + (kQ + a) * kRowWords);
-        dma8(bg, ob, rows + (kQ + b) * kRowWords);
+        for (int p = 0; p < kPairs; ++p) {
+            const int a = 2 * p + 1, b = 2 * p + 2;
+            const int cx = kPairVel[p][0], cy = kPairVel[p][1], cz = kPairVel[p][2];
+            uint32_t oa = Xo[cx + 3] + (Yo[cy + 3] + Zo[cz + 3]);
+            uint32_t ob = Xo[3 - cx] + (Yo[3 - cy] + Zo[3 - cz]);
+            oa = copy ? cellR : oa;
+            ob = copy ? cellR : ob;
+            dma16(srcb + (uint64_t)a * nP, oa, rows + a * kSegment);
+            dma16(srcb + (uint64_t)b * nP, ob, rows + b * kSegment);
+        }
+    } else {
+        const uint64_t lk = copy ? 0ull : links;
+#pragma unroll
+        for (int p = 0; p < kPairs; ++p) {
+            const int a = 2 * p + 1, b = 2 * p + 2;
+            const int cx = kPairVel[p][0], cy = kPairVel[p][1], cz = kPairVel[p][2];
+            uint32_t oa = Xo[cx + 3] + (Yo[cy + 3] + Zo[cz + 3]);
+            uint32_t ob = Xo[3 - cx] + (Yo[3 - cy] + Zo[3 - cz]);
+            oa = copy ? cellR : oa;
+            ob = copy ? cellR : ob;
+            gcbyte *pa = srcb + (uint64_t)a * nP, *pb = srcb + (uint64_t)b * nP;
+            gcbyte *sa = ((lk >> a) & 1ull) ? pb + cellR : pa + oa;
+            gcbyte *sb = ((lk >> b) & 1ull) ? pa + cellR : pb + ob;
+            dma16_at(sa, rows + a * kSegment);
+            dma16_at(sb, rows + b * kSegment);
+        }
     }
 }
+
+// The multipliers go out with the gather, except in the variants with
+// statistics: those hold more registers through the solve and load them
+// after the moments (loading them early there costs scratch).
+template <bool kStats>
+constexpr bool kLamLoaded = !kStats;
 
 // moments, Newton (kSolver 0; 1: the secant variant), sensor and relaxation
 // of one fluid cell whose gathered values sit in LDS; the results replace them
 template <bool kStats, int kSolver>
-__device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const Park &pk, int32_t (&acc)[kStatWords])
+__device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const Park &pk, double (&lam)[kM],
+                                        int32_t (&acc)[kStatWords])
 {
     using C = double;
     C rho = C(-0.0), j0 = C(-0.0), j1 = C(-0.0), j2 = C(-0.0), e = C(-0.0);
-    C sg = pk.get(kQ);
-    rho += pk.get(0);
+    const v2d r0 = pk.get(0);
+    C sg = r0.y;
+    rho += r0.x;
 #pragma unroll
     for (int p = 0; p < kPairs; ++p) {
-        const C fa = pk.get(2 * p + 1), fb = pk.get(2 * p + 2);
+        const v2d ra = pk.get(2 * p + 1), rb = pk.get(2 * p + 2);
+        const C fa = ra.x, fb = rb.x;
         const C sp = fa + fb, ap = fa - fb;
         rho += sp;
         j0 += C(kPairVel[p][0]) * ap;
         j1 += C(kPairVel[p][1]) * ap;
         j2 += C(kPairVel[p][2]) * ap;
         e += C(pair_q(p)) * sp;
-        sg += pk.get(kQ + 2 * p + 1) + pk.get(kQ + 2 * p + 2);
+        sg += ra.y + rb.y;
         // read the rows a few pairs at a time, not all at once
         if ((p & 1) == 1) __asm__ volatile("" ::: "memory");
     }
@@ -959,9 +1001,10 @@ __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const 
     gbyte *lamb = (gbyte *)d.lam;
     const uint64_t nL64 = (uint64_t)d.n * 8;
     const uint32_t cellL = cell * 8u;
-    C lam[kM];
+    if constexpr (!kLamLoaded<kStats>) {
 #pragma unroll
-    for (int k = 0; k < kM; ++k) lam[k] = gload<C>(splane(lamb + (uint64_t)k * nL64), cellL);
+        for (int k = 0; k < kM; ++k) lam[k] = gload<C>(splane(lamb + (uint64_t)k * nL64), cellL);
+    }
 
     C f0, fp[kPairs], fm[kPairs];
     int iters = 0;
@@ -991,7 +1034,7 @@ __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const 
     for (int i = 0; i < kQ; ++i) {
         const C e_i = (i == 0) ? f0 : (((i - 1) & 1) == 0 ? fp[(i - 1) >> 1] : fm[(i - 1) >> 1]);
         const C feq = rho * e_i;
-        eps += fabs(pk.get(i) - feq) * recip(feq);
+        eps += fabs(pk.get(i).x - feq) * recip(feq);
     }
     eps *= C(1.0 / kQ);
     int br = 0;
@@ -1011,9 +1054,9 @@ __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const 
         const C e_i = (i == 0) ? f0 : (((i - 1) & 1) == 0 ? fp[(i - 1) >> 1] : fm[(i - 1) >> 1]);
         const C feq = rho * e_i;
         const C geq = dT * feq;
-        const C hf = pk.get(i), hg = pk.get(kQ + i);
-        pk.put(i, hf + omega * (feq - hf));
-        pk.put(kQ + i, hg + omega * (geq - hg));
+        const v2d h = pk.get(i);
+        const C hf = h.x, hg = h.y;
+        pk.put(i, v2d{hf + omega * (feq - hf), hg + omega * (geq - hg)});
     }
 
     if constexpr (kStats) {
@@ -1037,7 +1080,7 @@ template <bool kStats, int kSolver>
 __global__ __launch_bounds__(kBlockThreads, 1) void step_kernel_f64(const SlotTable *__restrict__ tab, int j,
                                                                    int64_t *__restrict__ stats)
 {
-    __shared__ uint32_t park[2 * kQ * f64::kRowWords];
+    __shared__ f64::v2d park[kWavesPerBlock * kQ * kSegment];
     int32_t acc[kStatWords] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int total = tab->total_blocks;
     const int xcd = blockIdx.x & 7;
@@ -1046,11 +1089,11 @@ __global__ __launch_bounds__(kBlockThreads, 1) void step_kernel_f64(const SlotTa
     const int hi = (int)(((int64_t)total * (xcd + 1)) >> 3);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    f64::lds_u32 *const rows0 = (f64::lds_u32 *)park + wave * (2 * kSegment);
+    f64::lds_v2d *const rows0 = (f64::lds_v2d *)park + wave * (kQ * kSegment);
     for (int b = lo + (int)(blockIdx.x >> 3); b < hi; b += per_xcd) {
-        // the 156 row addresses are cheap to form; keep the compiler from
+        // the 39 row addresses are cheap to form; keep the compiler from
         // hoisting them out of the loop into registers
-        f64::lds_u32 *rows = rows0;
+        f64::lds_v2d *rows = rows0;
         __asm__ volatile("" : "+s"(rows));
         const f64::Park pk{rows + lane};
         const int s = find_slot(tab, b);
@@ -1064,8 +1107,6 @@ __global__ __launch_bounds__(kBlockThreads, 1) void step_kernel_f64(const SlotTa
         const int z = row / d.ny;
         const int x = segx * kSegment + lane;
         const uint32_t cell0 = (uint32_t)(segx * kSegment) + (uint32_t)d.nx * (uint32_t)row;
-        // 16-byte stores of two cells need an even first cell
-        const bool full = (segx * kSegment + kSegment <= d.nx) && (d.nx % 2 == 0);
         const bool in_grid = x < d.nx;
         const uint32_t cell = cell0 + (uint32_t)lane;
         const int par = (d.parity0 + j) & 1;
@@ -1075,16 +1116,24 @@ __global__ __launch_bounds__(kBlockThreads, 1) void step_kernel_f64(const SlotTa
         uint64_t links = 0;
         if (fluid && d.has_links) links = d.links[cell];
         if (links >> 63) fluid = false;  // solid cells pass through unchanged
-        // the memory phase (row stores, then the next gather) issues ahead of
-        // the other waves' arithmetic
+        const bool linked = __builtin_amdgcn_ballot_w64(fluid && links != 0) != 0;
+        // the gather's 39 transfers and the 13 multiplier loads go out
+        // together and are waited for once
         __builtin_amdgcn_s_setprio(1);
-        if (in_grid) f64::gather(d, srcb, x, y, z, cell, links, !fluid, rows);
+        if (in_grid) f64::gather(d, srcb, x, y, z, cell, links, !fluid, linked, rows);
+        double lam[kM];
+        if (f64::kLamLoaded<kStats> && fluid) {
+            gcbyte *lamb = (gcbyte *)d.lam;
+            const uint64_t nL64 = (uint64_t)d.n * 8;
+#pragma unroll
+            for (int k = 0; k < kM; ++k) lam[k] = gload<double>(f64::splane(lamb + (uint64_t)k * nL64), cell * 8u);
+        }
         __builtin_amdgcn_s_setprio(0);
         f32::wait_vmem();
         int32_t it_cell = 0;
         if (fluid) {
             const int32_t before = acc[0];
-            f64::collide<kStats, kSolver>(d, cell, pk, acc);
+            f64::collide<kStats, kSolver>(d, cell, pk, lam, acc);
             it_cell = acc[0] - before;
         }
         if constexpr (kStats) {
@@ -1092,28 +1141,17 @@ __global__ __launch_bounds__(kBlockThreads, 1) void step_kernel_f64(const SlotTa
             acc[8] += lane == 0 ? wmax : 0;
             acc[9] += lane == 0 ? 1 : 0;
         }
-        // store the wave's rows
+        // store the wave's records: one 16-byte store per lane and velocity,
+        // 1 KB contiguous per full row
         __builtin_amdgcn_s_setprio(1);
-        const uint64_t nS64 = (uint64_t)d.n * 8;
-        if (full) {
-            // lanes 32r..32r+31 store row i0 + r, two cells each
-            const int r = lane >> 5, c2 = (lane & 31) * 2;
-            uint32_t voff = (uint32_t)r * (uint32_t)nS64 + (cell0 + (uint32_t)c2) * 8u;
-            const f64::lds_u32 *lrow = rows + r * f64::kRowWords + c2;
-            __asm__ volatile("" : "+v"(voff));
+        if (in_grid) {
+            const uint64_t nP = (uint64_t)d.n * f64::kRec;
+            const uint32_t cellR = cell * f64::kRec;
 #pragma unroll
-            for (int i0 = 0; i0 < 2 * kQ; i0 += 2) {
-                const f64::v2u lw = *reinterpret_cast<const f64::v2u __attribute__((address_space(3))) *>(
-                    lrow + i0 * f64::kRowWords);
-                const f64::v2u hw = *reinterpret_cast<const f64::v2u __attribute__((address_space(3))) *>(
-                    lrow + i0 * f64::kRowWords + kSegment);
-                const f64::v4u v = {lw.x, hw.x, lw.y, hw.y};
+            for (int i = 0; i < kQ; ++i)
                 __builtin_nontemporal_store(
-                    v, reinterpret_cast<f64::v4u __attribute__((address_space(1))) *>(dstb + (uint64_t)i0 * nS64 + voff));
-            }
-        } else if (in_grid) {
-#pragma unroll
-            for (int i = 0; i < 2 * kQ; ++i) gstore<double>(dstb + (uint64_t)i * nS64, cell * 8u, pk.get(i));
+                    pk.get(i), reinterpret_cast<f64::v2d __attribute__((address_space(1))) *>(
+                                   f64::splane(dstb + (uint64_t)i * nP) + cellR));
         }
     }
     if constexpr (kStats) {
@@ -1162,10 +1200,10 @@ __global__ __launch_bounds__(256) void init_kernel(SlotDesc d, const double *__r
             vg = (geq - (double)d.shift_w[kQ + i]) * (double)d.shell_inv_scale[1][shell(i)];
         }
         const S sf = static_cast<S>(vf), sg = static_cast<S>(vg);
-        b0[(int64_t)i * d.n + cell] = sf;
-        b1[(int64_t)i * d.n + cell] = sf;
-        b0[(int64_t)(kQ + i) * d.n + cell] = sg;
-        b1[(int64_t)(kQ + i) * d.n + cell] = sg;
+        b0[pidx<S>(i, cell, d.n)] = sf;
+        b1[pidx<S>(i, cell, d.n)] = sf;
+        b0[pidx<S>(kQ + i, cell, d.n)] = sg;
+        b1[pidx<S>(kQ + i, cell, d.n)] = sg;
     }
     C *lb = static_cast<C *>(d.lam);
 #pragma unroll
@@ -1223,8 +1261,8 @@ __global__ __launch_bounds__(256) void moments_kernel(SlotDesc d, int parity, do
             const S *b = static_cast<const S *>(d.buf[parity]);
             double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0, e = 0.0;
             for (int i = 0; i < kQ; ++i) {
-                double vf = (double)b[(int64_t)i * d.n + src];
-                double vg = (double)b[(int64_t)(kQ + i) * d.n + src];
+                double vf = (double)b[pidx<S>(i, src, d.n)];
+                double vg = (double)b[pidx<S>(kQ + i, src, d.n)];
                 if constexpr (StoreTraits<S>::kShift) {
                     vf = (double)d.shift_w[i] + vf * (double)d.shell_scale[0][shell(i)];
                     vg = (double)d.shift_w[kQ + i] + vg * (double)d.shell_scale[1][shell(i)];
@@ -1324,7 +1362,7 @@ __global__ void decode_pop_kernel(SlotDesc d, int parity, int pop, double *__res
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= d.n) return;
     const S *b = static_cast<const S *>(d.buf[parity]);
-    double v = (double)b[(int64_t)pop * d.n + c];
+    double v = (double)b[pidx<S>(pop, c, d.n)];
     if constexpr (StoreTraits<S>::kShift)
         v = (double)d.shift_w[pop] + v * (double)d.shell_scale[pop >= kQ][shell(pop % kQ)];
     out[c] = v;
@@ -1339,8 +1377,8 @@ __global__ void encode_pop_kernel(SlotDesc d, int pop, const double *__restrict_
     if constexpr (StoreTraits<S>::kShift)
         v = (v - (double)d.shift_w[pop]) * (double)d.shell_inv_scale[pop >= kQ][shell(pop % kQ)];
     const S s = static_cast<S>(v);
-    static_cast<S *>(d.buf[0])[(int64_t)pop * d.n + c] = s;
-    static_cast<S *>(d.buf[1])[(int64_t)pop * d.n + c] = s;
+    static_cast<S *>(d.buf[0])[pidx<S>(pop, c, d.n)] = s;
+    static_cast<S *>(d.buf[1])[pidx<S>(pop, c, d.n)] = s;
 }
 
 template <class C>
