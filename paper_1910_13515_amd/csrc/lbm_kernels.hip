@@ -68,6 +68,12 @@ struct Park {
     C *base;  // &lds[0][threadIdx.x]
     __device__ __forceinline__ void put(int i, C v) const { base[i * kBlockThreads] = v; }
     __device__ __forceinline__ C get(int i) const { return base[i * kBlockThreads]; }
+    // f_i and g_i together
+    __device__ __forceinline__ void put2(int i, C f, C g) const
+    {
+        put(i, f);
+        put(kQ + i, g);
+    }
 };
 
 // Running moments of the gathered populations: mass, momentum, and the
@@ -91,7 +97,7 @@ struct StoreTraits<_Float16> {
     static constexpr bool kShift = true;
     static constexpr bool kScale = true;  // deviations stored divided by a power of two per shell
     static constexpr int kWavesPerSimd = 2;
-    static constexpr bool kPaired = false;
+    static constexpr bool kPaired = true;  // one dword (f_i, g_i) per cell and velocity
 };
 
 // Where population pop (0..38 f, 39..77 g) of a cell sits in a population
@@ -432,47 +438,29 @@ __device__ __forceinline__ void dma4(gcbyte *gaddr, lds_float *row_base)
                                      (void __attribute__((address_space(3))) *)row_base, 4, 0, 0);
 }
 
-// a 2-byte transfer lands zero-extended in the lane's dword of the LDS row
-__device__ __forceinline__ void dma2(gcbyte *gaddr, lds_float *row_base)
-{
-    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)gaddr,
-                                     (void __attribute__((address_space(3))) *)row_base, 2, 0, 0);
-}
-
-template <int kBytes>
-__device__ __forceinline__ void dma(gcbyte *gaddr, lds_float *row_base)
-{
-    if constexpr (kBytes == 4) dma4(gaddr, row_base);
-    else dma2(gaddr, row_base);
-}
-
 __device__ __forceinline__ float uniform(float v)
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
 }
 
-// gather of one cell's 78 values (stored kBytes wide) into the wave's LDS
-// rows (row i at rows + i*256, one dword per lane); copy = the cell's own values
-template <int kBytes = 4>
+// gather of one cell's 78 FP32 values into the wave's LDS rows (row i at
+// rows + i*256, one dword per lane); copy = the cell's own values
 __device__ __forceinline__ void gather(const SlotDesc &d, gcbyte *srcb, int x, int y, int z, uint32_t cell,
                                        uint64_t links, bool copy, lds_float *rows)
 {
-    const uint64_t nS64 = (uint64_t)d.n * kBytes;
+    const uint64_t nS64 = (uint64_t)d.n * 4;
     const uint32_t nS = (uint32_t)nS64;
-    const uint32_t cellS = cell * (uint32_t)kBytes;
+    const uint32_t cellS = cell * 4u;
     const uint32_t nx = (uint32_t)d.nx, nxy = (uint32_t)d.nx * (uint32_t)d.ny;
     uint32_t Xo[7], Yo[7], Zo[7];
 #pragma unroll
     for (int c = -3; c <= 3; ++c) {
-        Xo[c + 3] = (uint32_t)source_coord(x, c, d.nx, d.axis[0] == kAxisPeriodic, d.neumann_lo[0], d.neumann_hi[0]) *
-                    (uint32_t)kBytes;
-        Yo[c + 3] = (uint32_t)source_coord(y, c, d.ny, d.axis[1] == kAxisPeriodic, d.neumann_lo[1], d.neumann_hi[1]) *
-                    nx * (uint32_t)kBytes;
-        Zo[c + 3] = (uint32_t)source_coord(z, c, d.nz, d.axis[2] == kAxisPeriodic, d.neumann_lo[2], d.neumann_hi[2]) *
-                    nxy * (uint32_t)kBytes;
+        Xo[c + 3] = (uint32_t)source_coord(x, c, d.nx, d.axis[0] == kAxisPeriodic, d.neumann_lo[0], d.neumann_hi[0]) * 4u;
+        Yo[c + 3] = (uint32_t)source_coord(y, c, d.ny, d.axis[1] == kAxisPeriodic, d.neumann_lo[1], d.neumann_hi[1]) * nx * 4u;
+        Zo[c + 3] = (uint32_t)source_coord(z, c, d.nz, d.axis[2] == kAxisPeriodic, d.neumann_lo[2], d.neumann_hi[2]) * nxy * 4u;
     }
-    dma<kBytes>(srcb + cellS, rows);
-    dma<kBytes>(srcb + (uint64_t)kQ * nS64 + cellS, rows + kQ * kBlockThreads);
+    dma4(srcb + cellS, rows);
+    dma4(srcb + (uint64_t)kQ * nS64 + cellS, rows + kQ * kBlockThreads);
 #pragma unroll
     for (int p = 0; p < kPairs; ++p) {
         const int a = 2 * p + 1, b = 2 * p + 2;
@@ -485,31 +473,83 @@ __device__ __forceinline__ void gather(const SlotDesc &d, gcbyte *srcb, int x, i
         ob = copy ? nS + cellS : ob;
         gcbyte *bf = srcb + (uint64_t)a * nS64;
         gcbyte *bg = srcb + (uint64_t)(kQ + a) * nS64;
-        dma<kBytes>(bf + oa, rows + a * kBlockThreads);
-        dma<kBytes>(bf + ob, rows + b * kBlockThreads);
-        dma<kBytes>(bg + oa, rows + (kQ + a) * kBlockThreads);
-        dma<kBytes>(bg + ob, rows + (kQ + b) * kBlockThreads);
+        dma4(bf + oa, rows + a * kBlockThreads);
+        dma4(bf + ob, rows + b * kBlockThreads);
+        dma4(bg + oa, rows + (kQ + a) * kBlockThreads);
+        dma4(bg + ob, rows + (kQ + b) * kBlockThreads);
     }
 }
 
-// FP16 storage seen through the FP32 park: a row word holds the stored half
-// (zero-extended); reads decode (times the shell scale), writes encode
+// gather of one cell's 39 paired FP16 words (f_i in the low half, g_i in the
+// high half) into the wave's LDS rows (row i at rows + i*256, one dword per
+// lane); copy = the cell's own words.  A blocked link reads the opposite
+// velocity's word at the cell itself, in another plane: waves with such a
+// link (linked, uniform) take per-lane addresses, the others a uniform plane
+// base plus a 32-bit offset.
+__device__ __forceinline__ void gather_paired(const SlotDesc &d, gcbyte *srcb, int x, int y, int z, uint32_t cell,
+                                              uint64_t links, bool copy, bool linked, lds_float *rows)
+{
+    const uint64_t nP = (uint64_t)d.n * 4;
+    const uint32_t cellS = cell * 4u;
+    const uint32_t nx = (uint32_t)d.nx, nxy = (uint32_t)d.nx * (uint32_t)d.ny;
+    uint32_t Xo[7], Yo[7], Zo[7];
+#pragma unroll
+    for (int c = -3; c <= 3; ++c) {
+        Xo[c + 3] = (uint32_t)source_coord(x, c, d.nx, d.axis[0] == kAxisPeriodic, d.neumann_lo[0], d.neumann_hi[0]) * 4u;
+        Yo[c + 3] = (uint32_t)source_coord(y, c, d.ny, d.axis[1] == kAxisPeriodic, d.neumann_lo[1], d.neumann_hi[1]) * nx * 4u;
+        Zo[c + 3] = (uint32_t)source_coord(z, c, d.nz, d.axis[2] == kAxisPeriodic, d.neumann_lo[2], d.neumann_hi[2]) * nxy * 4u;
+    }
+    dma4(srcb + cellS, rows);
+    const uint64_t lk = copy ? 0ull : links;
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p) {
+        const int a = 2 * p + 1, b = 2 * p + 2;
+        const int cx = kPairVel[p][0], cy = kPairVel[p][1], cz = kPairVel[p][2];
+        uint32_t oa = Xo[cx + 3] + (Yo[cy + 3] + Zo[cz + 3]);
+        uint32_t ob = Xo[3 - cx] + (Yo[3 - cy] + Zo[3 - cz]);
+        oa = copy ? cellS : oa;
+        ob = copy ? cellS : ob;
+        gcbyte *pa = srcb + (uint64_t)a * nP, *pb = srcb + (uint64_t)b * nP;
+        if (!linked) {
+            dma4(pa + oa, rows + a * kBlockThreads);
+            dma4(pb + ob, rows + b * kBlockThreads);
+        } else {
+            gcbyte *sa = ((lk >> a) & 1ull) ? pb + cellS : pa + oa;
+            gcbyte *sb = ((lk >> b) & 1ull) ? pa + cellS : pb + ob;
+            dma4(sa, rows + a * kBlockThreads);
+            dma4(sb, rows + b * kBlockThreads);
+        }
+    }
+}
+
+// Paired FP16 storage seen through the FP32 park: row word i holds the stored
+// halves of f_i (low) and g_i (high); reads decode (times the shell scale),
+// writes encode
 struct ParkHalf {
     uint32_t *base;  // &lds_words[0][threadIdx.x]
     const float *scale;      // shell scales of f (0..5) then g (6..11)
     const float *inv_scale;
     __device__ __forceinline__ float get(int i) const
     {
-        const uint16_t h = (uint16_t)base[i * kBlockThreads];
-        const int k = (i < kQ ? 0 : 6) + shell(i < kQ ? i : i - kQ);
-        return (float)__builtin_bit_cast(_Float16, h) * scale[k];
+        const bool hi = i >= kQ;
+        const int v = hi ? i - kQ : i;
+        const uint32_t w = base[v * kBlockThreads];
+        const uint16_t h = hi ? (uint16_t)(w >> 16) : (uint16_t)w;
+        return (float)__builtin_bit_cast(_Float16, h) * scale[(hi ? 6 : 0) + shell(v)];
     }
     __device__ __forceinline__ void put(int i, float v) const
     {
-        // a 16-bit write of the low half; the high half stays zero
-        const int k = (i < kQ ? 0 : 6) + shell(i < kQ ? i : i - kQ);
-        *reinterpret_cast<uint16_t *>(base + i * kBlockThreads) =
-            __builtin_bit_cast(uint16_t, (_Float16)(v * inv_scale[k]));
+        // a 16-bit write of one half
+        const bool hi = i >= kQ;
+        const int q = hi ? i - kQ : i;
+        *(reinterpret_cast<uint16_t *>(base + q * kBlockThreads) + (hi ? 1 : 0)) =
+            __builtin_bit_cast(uint16_t, (_Float16)(v * inv_scale[(hi ? 6 : 0) + shell(q)]));
+    }
+    __device__ __forceinline__ void put2(int i, float f, float g) const
+    {
+        const uint32_t lo = __builtin_bit_cast(uint16_t, (_Float16)(f * inv_scale[shell(i)]));
+        const uint32_t hi = __builtin_bit_cast(uint16_t, (_Float16)(g * inv_scale[6 + shell(i)]));
+        base[i * kBlockThreads] = lo | (hi << 16);
     }
 };
 
@@ -606,8 +646,7 @@ __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const 
         const C feq = rho * e_i;
         const C geq = dT * feq;
         const C hf = pk.get(i), hg = pk.get(kQ + i);
-        pk.put(i, hf + omega * ((feq - C(d.shift_w[i])) - hf));
-        pk.put(kQ + i, hg + omega * ((geq - C(d.shift_w[kQ + i])) - hg));
+        pk.put2(i, hf + omega * ((feq - C(d.shift_w[i])) - hf), hg + omega * ((geq - C(d.shift_w[kQ + i])) - hg));
     }
 
     acc[0] += iters;
@@ -732,16 +771,17 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f32(const SlotTa
 }
 
 // ---------------------------------------------------------------------------
-// FP16-shifted step with the FP32 step's structure: 2-byte transfers global
-// -> LDS (each lands zero-extended in the lane's dword of the row), FP32
-// arithmetic through the decoding park, results encoded back into the row
-// words, and full rows leaving as 16-byte-per-lane stores of eight cells
-// (eight rows per instruction).
+// FP16-shifted step with the FP32 step's structure.  Storage is paired: one
+// dword per cell and velocity holds the halves of f_i (low) and g_i (high),
+// so the gather is 39 dword transfers global -> LDS per 64-cell segment.
+// FP32 arithmetic runs through the decoding park, results are encoded back
+// into the row words, and full rows leave as 16-byte-per-lane stores of four
+// cells (four rows per instruction).
 template <bool kStats, bool kWide>
 __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f16(const SlotTable *__restrict__ tab, int j,
                                                                    int64_t *__restrict__ stats)
 {
-    __shared__ uint32_t park[2 * kQ * kBlockThreads];
+    __shared__ uint32_t park[kQ * kBlockThreads];
     int32_t acc[kStatWords] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int total = tab->total_blocks;
     const int xcd = blockIdx.x & 7;
@@ -763,8 +803,8 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f16(const SlotTa
         const int z = row / d.ny;
         const int x = segx * kSegment + lane;
         const uint32_t cell0 = (uint32_t)(segx * kSegment) + (uint32_t)d.nx * (uint32_t)row;
-        // 16-byte stores of eight cells need a row start on an 8-cell boundary
-        const bool full = (segx * kSegment + kSegment <= d.nx) && (d.nx % 8 == 0);
+        // 16-byte stores of four cells need a row start on a 4-cell boundary
+        const bool full = (segx * kSegment + kSegment <= d.nx) && (d.nx % 4 == 0);
         const bool in_grid = x < d.nx;
         const uint32_t cell = cell0 + (uint32_t)lane;
         const int par = (d.parity0 + j) & 1;
@@ -774,10 +814,11 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f16(const SlotTa
         uint64_t links = 0;
         if (fluid && d.has_links) links = d.links[cell];
         if (links >> 63) fluid = false;  // solid cells pass through unchanged
+        const bool linked = __builtin_amdgcn_ballot_w64(fluid && links != 0) != 0;
         // the memory phase (row stores, then the next gather) issues ahead of
         // the other waves' arithmetic
         __builtin_amdgcn_s_setprio(1);
-        if (in_grid) f32::gather<2>(d, srcb, x, y, z, cell, links, !fluid, rows);
+        if (in_grid) f32::gather_paired(d, srcb, x, y, z, cell, links, !fluid, linked, rows);
         __builtin_amdgcn_s_setprio(0);
         f32::wait_vmem();
         int32_t it_cell = 0;
@@ -795,50 +836,41 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f16(const SlotTa
         }
         // store the wave's rows
         __builtin_amdgcn_s_setprio(1);
-        const uint64_t nS64 = (uint64_t)d.n * 2;
+        const uint64_t nP = (uint64_t)d.n * 4;
         const uint32_t *col = park + wave * kSegment;
         typedef uint32_t v4u __attribute__((ext_vector_type(4)));
         if (full && !kWide) {
-            // lanes 8r..8r+7 store row i0 + r, eight cells each: one uniform
-            // base per group of 8 rows and one 32-bit lane offset (8 planes
-            // of 2n bytes stay below 2^32 for n < 2^28)
-            const int r = lane >> 3, c8 = (lane & 7) * 8;
-            uint32_t voff = (uint32_t)r * (uint32_t)nS64 + (cell0 + (uint32_t)c8) * 2u;
-            const uint32_t *lcol = col + r * kBlockThreads + c8;
+            // lanes 16r..16r+15 store row i0 + r, four cells each: one uniform
+            // base per group of 4 rows and one 32-bit lane offset (4 planes
+            // of 4n bytes stay below 2^32 for n < 2^28)
+            const int r = lane >> 4, c4 = (lane & 15) * 4;
+            uint32_t voff = (uint32_t)r * (uint32_t)nP + (cell0 + (uint32_t)c4) * 4u;
+            const uint32_t *lcol = col + r * kBlockThreads + c4;
             __asm__ volatile("" : "+v"(voff));
 #pragma unroll
-            for (int i0 = 0; i0 < 2 * kQ; i0 += 8) {
-                if (i0 + r < 2 * kQ) {
-                    const v4u w0 = *reinterpret_cast<const v4u *>(lcol + i0 * kBlockThreads);
-                    const v4u w1 = *reinterpret_cast<const v4u *>(lcol + i0 * kBlockThreads + 4);
-                    // every word holds a half zero-extended (the gather's
-                    // 2-byte transfers and the collision's writes alike)
-                    const v4u v = {w0.x | (w0.y << 16), w0.z | (w0.w << 16), w1.x | (w1.y << 16),
-                                   w1.z | (w1.w << 16)};
+            for (int i0 = 0; i0 < kQ; i0 += 4) {
+                if (i0 + r < kQ) {
+                    const v4u v = *reinterpret_cast<const v4u *>(lcol + i0 * kBlockThreads);
                     __builtin_nontemporal_store(
-                        v, reinterpret_cast<v4u __attribute__((address_space(1))) *>(dstb + (uint64_t)i0 * nS64 + voff));
+                        v, reinterpret_cast<v4u __attribute__((address_space(1))) *>(dstb + (uint64_t)i0 * nP + voff));
                 }
             }
         } else if (full) {
             // 2^28 cells or more: the same stores from a 64-bit lane address
-            const int r = lane >> 3, c8 = (lane & 7) * 8;
-            gbyte *lane_base = dstb + (uint64_t)r * nS64 + (uint64_t)(cell0 + (uint32_t)c8) * 2u;
-            const uint32_t *lcol = col + r * kBlockThreads + c8;
+            const int r = lane >> 4, c4 = (lane & 15) * 4;
+            gbyte *lane_base = dstb + (uint64_t)r * nP + (uint64_t)(cell0 + (uint32_t)c4) * 4u;
+            const uint32_t *lcol = col + r * kBlockThreads + c4;
 #pragma unroll
-            for (int i0 = 0; i0 < 2 * kQ; i0 += 8) {
-                if (i0 + r < 2 * kQ) {
-                    const v4u w0 = *reinterpret_cast<const v4u *>(lcol + i0 * kBlockThreads);
-                    const v4u w1 = *reinterpret_cast<const v4u *>(lcol + i0 * kBlockThreads + 4);
-                    const v4u v = {w0.x | (w0.y << 16), w0.z | (w0.w << 16), w1.x | (w1.y << 16),
-                                   w1.z | (w1.w << 16)};
+            for (int i0 = 0; i0 < kQ; i0 += 4) {
+                if (i0 + r < kQ) {
+                    const v4u v = *reinterpret_cast<const v4u *>(lcol + i0 * kBlockThreads);
                     __builtin_nontemporal_store(
-                        v, reinterpret_cast<v4u __attribute__((address_space(1))) *>(lane_base + (uint64_t)i0 * nS64));
+                        v, reinterpret_cast<v4u __attribute__((address_space(1))) *>(lane_base + (uint64_t)i0 * nP));
                 }
             }
         } else if (in_grid) {
 #pragma unroll
-            for (int i = 0; i < 2 * kQ; ++i)
-                gstore<uint16_t>(dstb + (uint64_t)i * nS64, cell * 2u, (uint16_t)col[i * kBlockThreads + lane]);
+            for (int i = 0; i < kQ; ++i) gstore<uint32_t>(dstb + (uint64_t)i * nP, cell * 4u, col[i * kBlockThreads + lane]);
         }
     }
     if constexpr (kStats) {
