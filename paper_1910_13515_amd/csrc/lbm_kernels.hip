@@ -960,6 +960,9 @@ __device__ __forceinline__ void gather(const SlotDesc &d, gcbyte *srcb, int x, i
     source_offsets(d, x, y, z, Xo, Yo, Zo);
     dma16(srcb, cellR, rows);
     if (!linked) {
+        // plane bases advance by one plane per transfer (two scalar adds
+        // instead of a 64-bit multiply per plane)
+        gcbyte *pl = srcb;
 #pragma unroll
         for (int p = 0; p < kPairs; ++p) {
             const int a = 2 * p + 1, b = 2 * p + 2;
@@ -968,8 +971,10 @@ __device__ __forceinline__ void gather(const SlotDesc &d, gcbyte *srcb, int x, i
             uint32_t ob = Xo[3 - cx] + (Yo[3 - cy] + Zo[3 - cz]);
             oa = copy ? cellR : oa;
             ob = copy ? cellR : ob;
-            dma16(srcb + (uint64_t)a * nP, oa, rows + a * kSegment);
-            dma16(srcb + (uint64_t)b * nP, ob, rows + b * kSegment);
+            pl = splane(pl + nP);
+            dma16(pl, oa, rows + a * kSegment);
+            pl = splane(pl + nP);
+            dma16(pl, ob, rows + b * kSegment);
         }
     } else {
         const uint64_t lk = copy ? 0ull : links;
@@ -1055,7 +1060,10 @@ __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const 
     const bool failed = status == kFailed;
     if (!failed) {
 #pragma unroll
-        for (int k = 0; k < kM; ++k) gstore<C>(splane(lamb + (uint64_t)k * nL64), cellL, lam[k]);
+        for (int k = 0; k < kM; ++k) {
+            gstore<C>(splane(lamb), cellL, lam[k]);
+            lamb += nL64;
+        }
     } else {
         gstore<C>(splane(lamb), cellL, __builtin_nan(""));  // the failure mark; lambda_1..12 kept
     }
@@ -1158,7 +1166,10 @@ __global__ __launch_bounds__(kBlockThreads, 1) void step_kernel_f64(const SlotTa
             gcbyte *lamb = (gcbyte *)d.lam;
             const uint64_t nL64 = (uint64_t)d.n * 8;
 #pragma unroll
-            for (int k = 0; k < kM; ++k) lam[k] = gload<double>(f64::splane(lamb + (uint64_t)k * nL64), cell * 8u);
+            for (int k = 0; k < kM; ++k) {
+                lam[k] = gload<double>(f64::splane(lamb), cell * 8u);
+                lamb += nL64;
+            }
         }
         __builtin_amdgcn_s_setprio(0);
         f32::wait_vmem();
@@ -1179,11 +1190,13 @@ __global__ __launch_bounds__(kBlockThreads, 1) void step_kernel_f64(const SlotTa
         if (in_grid) {
             const uint64_t nP = (uint64_t)d.n * f64::kRec;
             const uint32_t cellR = cell * f64::kRec;
+            gbyte *pl = f64::splane(dstb);
 #pragma unroll
-            for (int i = 0; i < kQ; ++i)
+            for (int i = 0; i < kQ; ++i) {
                 __builtin_nontemporal_store(
-                    pk.get(i), reinterpret_cast<f64::v2d __attribute__((address_space(1))) *>(
-                                   f64::splane(dstb + (uint64_t)i * nP) + cellR));
+                    pk.get(i), reinterpret_cast<f64::v2d __attribute__((address_space(1))) *>(pl + cellR));
+                pl = f64::splane(pl + nP);
+            }
         }
     }
     if constexpr (kStats) {
