@@ -915,6 +915,11 @@ __device__ __forceinline__ gcbyte *splane(gcbyte *p)
 struct Park {
     lds_v2d *base;  // the lane's record in row 0 of its wave
     __device__ __forceinline__ v2d get(int i) const { return base[i * kSegment]; }
+    // f_i alone (an 8-byte read)
+    __device__ __forceinline__ double get_f(int i) const
+    {
+        return *reinterpret_cast<const double __attribute__((address_space(3))) *>(base + i * kSegment);
+    }
     __device__ __forceinline__ void put(int i, v2d v) const { base[i * kSegment] = v; }
 };
 
@@ -995,6 +1000,9 @@ __device__ __forceinline__ void gather(const SlotDesc &d, gcbyte *srcb, int x, i
     }
 }
 
+// LDS records read per group in the sensor, the relaxation and the stores
+constexpr int kChunk = 8;
+
 // The multipliers go out with the gather, except in the variants with
 // statistics: those hold more registers through the solve and load them
 // after the moments (loading them early there costs scratch).
@@ -1068,13 +1076,26 @@ __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const 
         gstore<C>(splane(lamb), cellL, __builtin_nan(""));  // the failure mark; lambda_1..12 kept
     }
 
-    // Knudsen sensor over f (Eq. eq:DeltaAvg) and relaxation branch (Eq. eq:alpha)
+    // Knudsen sensor over f (Eq. eq:DeltaAvg) and relaxation branch (Eq. eq:alpha).
+    // The records are read kChunk at a time, each group's LDS reads issued
+    // together (a lone wave has no other wave to cover their latency).
     C eps = C(0);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-        const C e_i = (i == 0) ? f0 : (((i - 1) & 1) == 0 ? fp[(i - 1) >> 1] : fm[(i - 1) >> 1]);
-        const C feq = rho * e_i;
-        eps += fabs(pk.get(i).x - feq) * recip(feq);
+    for (int i0 = 0; i0 < kQ; i0 += kChunk) {
+        C hf[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k)
+            if (i0 + k < kQ) hf[k] = pk.get_f(i0 + k);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
+            const int i = i0 + k;
+            if (i < kQ) {
+                const C e_i = (i == 0) ? f0 : (((i - 1) & 1) == 0 ? fp[(i - 1) >> 1] : fm[(i - 1) >> 1]);
+                const C feq = rho * e_i;
+                eps += fabs(hf[k] - feq) * recip(feq);
+            }
+        }
     }
     eps *= C(1.0 / kQ);
     int br = 0;
@@ -1090,13 +1111,23 @@ __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const 
     const C dT = C(d.delta) * T;
     __asm__ volatile("" ::: "memory");
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-        const C e_i = (i == 0) ? f0 : (((i - 1) & 1) == 0 ? fp[(i - 1) >> 1] : fm[(i - 1) >> 1]);
-        const C feq = rho * e_i;
-        const C geq = dT * feq;
-        const v2d h = pk.get(i);
-        const C hf = h.x, hg = h.y;
-        pk.put(i, v2d{hf + omega * (feq - hf), hg + omega * (geq - hg)});
+    for (int i0 = 0; i0 < kQ; i0 += kChunk) {
+        v2d h[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k)
+            if (i0 + k < kQ) h[k] = pk.get(i0 + k);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
+            const int i = i0 + k;
+            if (i < kQ) {
+                const C e_i = (i == 0) ? f0 : (((i - 1) & 1) == 0 ? fp[(i - 1) >> 1] : fm[(i - 1) >> 1]);
+                const C feq = rho * e_i;
+                const C geq = dT * feq;
+                const C hf = h[k].x, hg = h[k].y;
+                pk.put(i, v2d{hf + omega * (feq - hf), hg + omega * (geq - hg)});
+            }
+        }
     }
 
     if constexpr (kStats) {
@@ -1192,10 +1223,20 @@ __global__ __launch_bounds__(kBlockThreads, 1) void step_kernel_f64(const SlotTa
             const uint32_t cellR = cell * f64::kRec;
             gbyte *pl = f64::splane(dstb);
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) {
-                __builtin_nontemporal_store(
-                    pk.get(i), reinterpret_cast<f64::v2d __attribute__((address_space(1))) *>(pl + cellR));
-                pl = f64::splane(pl + nP);
+            for (int i0 = 0; i0 < kQ; i0 += f64::kChunk) {
+                f64::v2d h[f64::kChunk];
+#pragma unroll
+                for (int k = 0; k < f64::kChunk; ++k)
+                    if (i0 + k < kQ) h[k] = pk.get(i0 + k);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int k = 0; k < f64::kChunk; ++k) {
+                    if (i0 + k < kQ) {
+                        __builtin_nontemporal_store(
+                            h[k], reinterpret_cast<f64::v2d __attribute__((address_space(1))) *>(pl + cellR));
+                        pl = f64::splane(pl + nP);
+                    }
+                }
             }
         }
     }
