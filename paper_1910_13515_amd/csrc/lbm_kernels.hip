@@ -569,6 +569,9 @@ __device__ __forceinline__ void bounce_fix(const SlotDesc &d, const PK &pk, uint
     }
 }
 
+// parked values read per group in the sensor and the relaxation
+constexpr int kChunk = 8;
+
 // moments, Newton, sensor and relaxation of one fluid cell whose gathered
 // values sit in LDS; the results replace them
 template <class PK>
@@ -625,7 +628,28 @@ __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const 
     }
     project_invariants(f0, fp, fm, u, T, G, !failed);
 
-    const C eps = eps_sum<S, C>(d, rho, f0, fp, fm, pk, VelSeq{}) * C(1.0 / kQ);
+    // the Knudsen sensor with the parked values read kChunk at a time, each
+    // group's LDS reads issued together (same terms, same order as eps_sum)
+    C eps = C(-0.0);
+#pragma unroll
+    for (int i0 = 0; i0 < kQ; i0 += kChunk) {
+        C hv[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k)
+            if (i0 + k < kQ) hv[k] = pk.get(i0 + k);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
+            const int i = i0 + k;
+            if (i < kQ) {
+                const C e_i = (i == 0) ? f0 : (((i - 1) & 1) == 0 ? fp[(i - 1) >> 1] : fm[(i - 1) >> 1]);
+                const C feq = rho * e_i;
+                const C diff = (C(d.shift_w[i]) - feq) + hv[k];
+                eps += fabs(diff) * recip(feq);
+            }
+        }
+    }
+    eps *= C(1.0 / kQ);
     int br = 0;
     if (d.kn_relax) br = (eps < C(1e-2)) ? 0 : (eps < C(1e-1)) ? 1 : (eps < C(1)) ? 2 : 3;
     const C o0 = uniform(C(d.omega[0])), o1 = uniform(C(d.omega[1])), o2 = uniform(C(d.omega[2])),
@@ -641,12 +665,27 @@ __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const 
     const C dT = C(d.delta) * T;
     __asm__ volatile("" ::: "memory");
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-        const C e_i = (i == 0) ? f0 : (((i - 1) & 1) == 0 ? fp[(i - 1) >> 1] : fm[(i - 1) >> 1]);
-        const C feq = rho * e_i;
-        const C geq = dT * feq;
-        const C hf = pk.get(i), hg = pk.get(kQ + i);
-        pk.put2(i, hf + omega * ((feq - C(d.shift_w[i])) - hf), hg + omega * ((geq - C(d.shift_w[kQ + i])) - hg));
+    for (int i0 = 0; i0 < kQ; i0 += kChunk) {
+        C hf[kChunk], hg[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
+            if (i0 + k < kQ) {
+                hf[k] = pk.get(i0 + k);
+                hg[k] = pk.get(kQ + i0 + k);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
+            const int i = i0 + k;
+            if (i < kQ) {
+                const C e_i = (i == 0) ? f0 : (((i - 1) & 1) == 0 ? fp[(i - 1) >> 1] : fm[(i - 1) >> 1]);
+                const C feq = rho * e_i;
+                const C geq = dT * feq;
+                pk.put2(i, hf[k] + omega * ((feq - C(d.shift_w[i])) - hf[k]),
+                        hg[k] + omega * ((geq - C(d.shift_w[kQ + i])) - hg[k]));
+            }
+        }
     }
 
     acc[0] += iters;
