@@ -75,9 +75,11 @@ std::string validate(const lbm_params *p)
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return "grid dimensions must be >= 1";
     const int64_t n = (int64_t)p->nx * p->ny * p->nz;
     if (p->storage < LBM_STORE_FP64 || p->storage > LBM_STORE_FP16_SHIFTED) return "unknown storage mode";
-    // the gathers address two population arrays (a velocity pair) from one
-    // base with 32-bit byte offsets: n < 2^28 in FP64, 2^29 in FP32, 2^30 in
-    // FP16 (the row stores switch to 64-bit lane addresses above 2^28 cells)
+    // the gathers address one velocity's plane (FP64 and FP16: 16- and
+    // 4-byte records of f_i and g_i) or, in FP32, a velocity pair's two
+    // arrays from one base with 32-bit byte offsets: n < 2^28 in FP64, 2^29
+    // in FP32, 2^30 in FP16 (the row stores switch to 64-bit lane addresses
+    // above 2^28 cells)
     if (2 * n * storage_bytes(p->storage) >= ((int64_t)1 << 32)) return "grid too large for this storage mode";
     if (p->shift_ref < 0 || p->shift_ref > 1) return "shift_ref must be 0 or 1";
     const int dims[3] = {p->nx, p->ny, p->nz};

@@ -1,10 +1,12 @@
 """The step at the largest grids the library takes, in every storage mode.
 
 The kernels address a solve's populations with 32-bit byte offsets from
-per-plane bases where they can: a gather reaches across a velocity pair (2
-planes), so lbm_create takes fewer than 2^28 cells in FP64, 2^29 in FP32 and
-2^30 in FP16.  The FP32 and FP16 row stores span 4 and 8 planes; above 2^28
-cells they switch from a 32-bit lane offset to a 64-bit lane address.  Device
+per-plane bases where they can: an FP32 gather reaches across a velocity
+pair (2 planes of 4n bytes), an FP64 or FP16 gather across one velocity's
+plane of paired records (16n and 4n bytes), so lbm_create takes fewer than
+2^28 cells in FP64, 2^29 in FP32 and 2^30 in FP16.  The FP32 and FP16 row
+stores span 4 planes of 4n bytes; above 2^28 cells they switch from a 32-bit
+lane offset to a 64-bit lane address.  Device
 memory bounds every mode before its offset bound (FP64 at 1.4 kB per cell,
 FP32 at 0.68 kB, FP16 at 0.42 kB).
 
