@@ -1049,10 +1049,11 @@ template <bool kStats>
 constexpr bool kLamLoaded = !kStats;
 
 // moments, Newton (kSolver 0; 1: the secant variant), sensor and relaxation
-// of one fluid cell whose gathered values sit in LDS; the results replace them
+// of one fluid cell whose gathered values sit in LDS; the relaxed records go
+// straight to the destination buffer dstb (one 16-byte store per velocity)
 template <bool kStats, int kSolver>
 __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const Park &pk, double (&lam)[kM],
-                                        int32_t (&acc)[kStatWords])
+                                        gbyte *dstb, int32_t (&acc)[kStatWords])
 {
     using C = double;
     C rho = C(-0.0), j0 = C(-0.0), j1 = C(-0.0), j2 = C(-0.0), e = C(-0.0);
@@ -1149,6 +1150,9 @@ __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const 
     omega = failed ? C(0) : omega;
     const C dT = C(d.delta) * T;
     __asm__ volatile("" ::: "memory");
+    const uint64_t nP = (uint64_t)d.n * kRec;
+    const uint32_t cellR = cell * kRec;
+    gbyte *pl = splane(dstb);
 #pragma unroll
     for (int i0 = 0; i0 < kQ; i0 += kChunk) {
         v2d h[kChunk];
@@ -1164,7 +1168,9 @@ __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const 
                 const C feq = rho * e_i;
                 const C geq = dT * feq;
                 const C hf = h[k].x, hg = h[k].y;
-                pk.put(i, v2d{hf + omega * (feq - hf), hg + omega * (geq - hg)});
+                __builtin_nontemporal_store(v2d{hf + omega * (feq - hf), hg + omega * (geq - hg)},
+                                            reinterpret_cast<v2d __attribute__((address_space(1))) *>(pl + cellR));
+                pl = splane(pl + nP);
             }
         }
     }
@@ -1246,7 +1252,7 @@ __global__ __launch_bounds__(kBlockThreads, 1) void step_kernel_f64(const SlotTa
         int32_t it_cell = 0;
         if (fluid) {
             const int32_t before = acc[0];
-            f64::collide<kStats, kSolver>(d, cell, pk, lam, acc);
+            f64::collide<kStats, kSolver>(d, cell, pk, lam, dstb, acc);
             it_cell = acc[0] - before;
         }
         if constexpr (kStats) {
@@ -1254,10 +1260,11 @@ __global__ __launch_bounds__(kBlockThreads, 1) void step_kernel_f64(const SlotTa
             acc[8] += lane == 0 ? wmax : 0;
             acc[9] += lane == 0 ? 1 : 0;
         }
-        // store the wave's records: one 16-byte store per lane and velocity,
-        // 1 KB contiguous per full row
+        // cells that are not collided (solid, frozen or Neumann layers) pass
+        // their gathered records through: one 16-byte store per lane and
+        // velocity
         __builtin_amdgcn_s_setprio(1);
-        if (in_grid) {
+        if (in_grid && !fluid) {
             const uint64_t nP = (uint64_t)d.n * f64::kRec;
             const uint32_t cellR = cell * f64::kRec;
             gbyte *pl = f64::splane(dstb);
