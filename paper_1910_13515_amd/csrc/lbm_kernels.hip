@@ -578,7 +578,6 @@ template <class PK>
 __device__ __forceinline__ void collide(const SlotDesc &d, uint32_t cell, const PK &pk, int32_t (&acc)[kStatWords])
 {
     using C = float;
-    using S = float;  // shifted storage: the sensor's formula is that of FP32
     C rho = C(d.ref_mass), j0 = C(d.ref_mom[0]), j1 = C(d.ref_mom[1]), j2 = C(d.ref_mom[2]), e = C(d.ref_energy);
     C sg = pk.get(kQ);
     rho += pk.get(0);
