@@ -569,8 +569,9 @@ __device__ __forceinline__ void bounce_fix(const SlotDesc &d, const PK &pk, uint
     }
 }
 
-// parked values read per group in the sensor and the relaxation
-constexpr int kChunk = 8;
+// parked values read per group in the sensor and the relaxation (two groups,
+// 20 and 19; measured against 8 and 13)
+constexpr int kChunk = 20;
 
 // moments, Newton, sensor and relaxation of one fluid cell whose gathered
 // values sit in LDS; the results replace them
