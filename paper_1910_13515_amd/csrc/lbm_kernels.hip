@@ -930,8 +930,9 @@ __global__ __launch_bounds__(kBlockThreads, 2) void step_kernel_f16(const SlotTa
 // 16-byte global -> LDS transfer per lane: 39 transfers of 1 KB per 64-cell
 // segment, all in flight together with the 13 multiplier loads (the vector
 // memory counter holds 63).  LDS row i of a wave holds the 64 records of
-// velocity i; results replace them and leave as one 16-byte store per lane
-// and velocity.  One wave per SIMD (the FP64 solve needs the register file).
+// velocity i; the relaxed records leave from registers as one 16-byte store
+// per lane and velocity.  One wave per SIMD (the FP64 solve needs the
+// register file).
 namespace f64 {
 
 typedef double v2d __attribute__((ext_vector_type(2)));
@@ -959,7 +960,6 @@ struct Park {
     {
         return *reinterpret_cast<const double __attribute__((address_space(3))) *>(base + i * kSegment);
     }
-    __device__ __forceinline__ void put(int i, v2d v) const { base[i * kSegment] = v; }
 };
 
 // one 16-byte transfer per lane into LDS row `row` (the hardware places lane
